@@ -1,0 +1,204 @@
+"""CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Python bindings for ``oracle/tc_oracle.c``: a plain, slow, single-threaded
+implementation of what the device path computes, written from the paper
+(Kolountzakis, Miller, Peng, Tsourakakis, arXiv:1011.0468).  Only the tests,
+the smoke check and the benchmark's CPU-baseline leg may import this module;
+the product package never does.  It imports nothing from the product package.
+
+All functions take / return numpy arrays.  A normalised graph is the tuple
+``(n, row_ptr int64[n+1], col int32[2m])`` with sorted neighbour lists.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build():
+    """Compile the oracle with gcc: no fast-math, no floating-point contraction."""
+    src = os.path.join(_HERE, "tc_oracle.c")
+    tmp = _SO + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-fno-fast-math", "-o", tmp, src])
+    os.replace(tmp, _SO)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    L = ctypes.CDLL(_SO)
+    i64, i32, u64, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    P = ctypes.POINTER
+    L.or_normalise.argtypes = [i64, i64, P(i32), P(i32), P(i64), P(i32), P(i64)]
+    L.or_normalise.restype = ctypes.c_int
+    L.or_mix64.argtypes = [u64]
+    L.or_mix64.restype = u64
+    L.or_keep_threshold.argtypes = [dbl]
+    L.or_keep_threshold.restype = u64
+    L.or_keep.argtypes = [i32, i32, u64, u64]
+    L.or_keep.restype = ctypes.c_int
+    L.or_sample.argtypes = [i64, P(i64), P(i32), dbl, u64, P(i64), P(i32)]
+    L.or_sample.restype = i64
+    L.or_count_triangles.argtypes = [i64, P(i64), P(i32), P(i64)]
+    L.or_count_triangles.restype = i64
+    L.or_count_triangles_idorder.argtypes = [i64, P(i64), P(i32)]
+    L.or_count_triangles_idorder.restype = i64
+    L.or_count_bruteforce.argtypes = [i64, P(ctypes.c_uint8)]
+    L.or_count_bruteforce.restype = i64
+    L.or_is_heavy.argtypes = [i64, i64, i32, i32]
+    L.or_is_heavy.restype = ctypes.c_int
+    L.or_count_split.argtypes = [i64, P(i64), P(i32), i32, i32, P(i64)]
+    L.or_count_split.restype = ctypes.c_int
+    L.or_estimate.argtypes = [i64, dbl]
+    L.or_estimate.restype = dbl
+    L.or_median_of_means.argtypes = [P(i64), i32, i32, dbl]
+    L.or_median_of_means.restype = dbl
+    L.or_rp_sign.argtypes = [u64, i64, i64]
+    L.or_rp_sign.restype = ctypes.c_int
+    L.or_quadform_a3.argtypes = [i64, P(i64), P(i32), P(i64)]
+    L.or_quadform_a3.restype = i64
+    L.or_rp_trace.argtypes = [i64, P(i64), P(i32), i32, u64, P(i64), P(dbl)]
+    L.or_rp_trace.restype = ctypes.c_int
+    L.or_rp_q.argtypes = [i64, P(i64), P(i32), i64, u64]
+    L.or_rp_q.restype = i64
+    _lib = L
+    return L
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _i64(a):
+    return _p(a, ctypes.c_int64)
+
+
+def _i32(a):
+    return _p(a, ctypes.c_int32)
+
+
+def normalise(n, src, dst):
+    """Simple undirected graph of the pairs: returns (n, row_ptr, col)."""
+    L = _load()
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    rp = np.empty(n + 1, np.int64)
+    col = np.empty(max(2 * len(src), 1), np.int32)
+    m = ctypes.c_int64(0)
+    rc = L.or_normalise(n, len(src), _i32(src), _i32(dst), _i64(rp), _i32(col), ctypes.byref(m))
+    if rc == 1:
+        raise ValueError("vertex id out of range")
+    if rc:
+        raise MemoryError("oracle normalise")
+    return n, rp, col[: 2 * m.value].copy()
+
+
+def mix64(z):
+    return int(_load().or_mix64(z & 0xFFFFFFFFFFFFFFFF))
+
+
+def keep_threshold(p):
+    return int(_load().or_keep_threshold(p))
+
+
+def keep(u, v, seed, p):
+    L = _load()
+    return bool(L.or_keep(u, v, seed, L.or_keep_threshold(p)))
+
+
+def sample(g, p, seed):
+    """G_p as (n, row_ptr_p, col_p); m' = len(col_p) // 2."""
+    n, rp, col = g
+    L = _load()
+    rpp = np.empty(n + 1, np.int64)
+    colp = np.empty(max(len(col), 1), np.int32)
+    L.or_sample(n, _i64(rp), _i32(col), p, seed, _i64(rpp), _i32(colp))
+    return n, rpp, colp[: rpp[n]].copy()
+
+
+def count(g, per_vertex=False):
+    """Triangle count (degree-ordered merge); optionally per lowest-ranked vertex."""
+    n, rp, col = g
+    L = _load()
+    pv = np.zeros(n, np.int64) if per_vertex else None
+    t = L.or_count_triangles(n, _i64(rp), _i32(col), _i64(pv) if per_vertex else None)
+    if t < 0:
+        raise MemoryError("oracle count")
+    return (int(t), pv) if per_vertex else int(t)
+
+
+def count_idorder(g):
+    n, rp, col = g
+    return int(_load().or_count_triangles_idorder(n, _i64(rp), _i32(col)))
+
+
+def count_bruteforce(adj):
+    adj = np.ascontiguousarray(adj, dtype=np.uint8)
+    return int(_load().or_count_bruteforce(adj.shape[0], _p(adj, ctypes.c_uint8)))
+
+
+def is_heavy(deg, m, a=1, b=1):
+    return bool(_load().or_is_heavy(deg, m, a, b))
+
+
+def count_split(g, a=1, b=1):
+    """dict(triangles, light, heavy, n_heavy, m) for the light/heavy split a/b."""
+    n, rp, col = g
+    out = np.zeros(5, np.int64)
+    rc = _load().or_count_split(n, _i64(rp), _i32(col), a, b, _i64(out))
+    if rc:
+        raise MemoryError("oracle split")
+    return dict(triangles=int(out[0]), light=int(out[1]), heavy=int(out[2]),
+                n_heavy=int(out[3]), m=int(out[4]))
+
+
+def estimate(T, p):
+    return float(_load().or_estimate(int(T), float(p)))
+
+
+def median_of_means(counts, num_groups, p):
+    c = np.ascontiguousarray(counts, dtype=np.int64)
+    return float(_load().or_median_of_means(_i64(c), len(c), num_groups, float(p)))
+
+
+def rp_sign(seed, l, i):
+    return int(_load().or_rp_sign(seed, l, i))
+
+
+def quadform_a3(g, x):
+    n, rp, col = g
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    return int(_load().or_quadform_a3(n, _i64(rp), _i32(col), _i64(x)))
+
+
+def rp_trace(g, k, seed):
+    """(q int64[k], triangle estimate)."""
+    n, rp, col = g
+    q = np.zeros(k, np.int64)
+    est = ctypes.c_double(0.0)
+    rc = _load().or_rp_trace(n, _i64(rp), _i32(col), k, seed, _i64(q), ctypes.byref(est))
+    if rc:
+        raise MemoryError("oracle rp")
+    return q, est.value
+
+
+def rp_q(g, l, seed):
+    n, rp, col = g
+    return int(_load().or_rp_q(n, _i64(rp), _i32(col), l, seed))
+
+
+def dense_adjacency(g):
+    n, rp, col = g
+    A = np.zeros((n, n), np.uint8)
+    for u in range(n):
+        A[u, col[rp[u]:rp[u + 1]]] = 1
+    return A
