@@ -1,0 +1,155 @@
+/*
+ * tc.h — C ABI of the MI355X (gfx950) degree-partitioned sampling triangle
+ * counter.
+ *
+ * The method is that of Kolountzakis, Miller, Peng and Tsourakakis,
+ * "Efficient Triangle Counting in Large Graphs via Degree-based Vertex
+ * Partitioning" (arXiv:1011.0468): sparsify the graph by keeping each edge
+ * with probability p (section 3.1), split the vertices at m^(1/2) into light
+ * and heavy sets (section 3.2), count exactly on the sparsified graph and
+ * rescale by 1/p^3 (section 3.1; the "Sparsified + Exact" columns of Table 2),
+ * plus the random-projection trace estimator of section 5.1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Graphs are simple and undirected (Table 1: G([n],E)); vertex ids are
+ *   0-based int32 in [0, n).  Input pairs may be directed, repeated or
+ *   self-loops; they are symmetrised and cleaned (section 4.1).
+ * - Every call returns a tc_status.  On error no output is written and a
+ *   message is available from tc_last_error() on the calling thread.  No C++
+ *   exception crosses this boundary.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *   enqueued on it; every call that produces host-visible outputs synchronises
+ *   that stream before returning.
+ * - Device memory is obtained through the allocator installed with
+ *   tc_set_allocator (default: a process-wide caching pool over hipMalloc).
+ * - Results are deterministic functions of (graph, p, seed, k).  tc_params
+ *   changes only the speed and the reported light/heavy split, never the
+ *   triangle count.
+ * - All counts are exact int64.  Limits: n <= 2^31-1, 2 * num_pairs <= 2^31-1
+ *   (int32 CSR), else TC_ERR_OVERFLOW.
+ */
+#ifndef TC_H_
+#define TC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TC_OK = 0,
+    TC_ERR_INVALID = 1,   /* bad argument: null pointer, id out of range, p outside (0,1], ... */
+    TC_ERR_OOM = 2,       /* the allocator returned NULL */
+    TC_ERR_DEVICE = 3,    /* a HIP runtime call or kernel launch failed */
+    TC_ERR_OVERFLOW = 4,  /* a size or an integer bound exceeds what the int32/int64 layout holds */
+    TC_ERR_BUDGET = 5     /* a request does not fit the memory budget of a server */
+} tc_status;
+
+/* Opaque graph handle: owns a device CSR (row_ptr int32[n+1], col int32[2m]
+   with each list sorted ascending, the row index of every CSR entry, and
+   deg int32[n]) until tc_graph_free. */
+typedef struct tc_graph_s* tc_graph;
+
+/* Light/heavy threshold (section 3.2 uses deg <= m^(1/2) for light).  A vertex
+   of the counted graph is heavy iff heavy_den^2 * deg^2 > heavy_num^2 * m,
+   evaluated in int64.  heavy_num = 0 makes every non-isolated vertex heavy. */
+typedef struct {
+    int32_t heavy_num;   /* default 1 */
+    int32_t heavy_den;   /* default 1, must be >= 1 */
+    int32_t use_tuned;   /* 1: take launch parameters from the autotuner's table */
+} tc_params;
+
+/* Result of one exact count (on the graph itself, or on one sparsified copy). */
+typedef struct {
+    int64_t triangles;        /* T = T_L + T_H */
+    int64_t light;            /* T_L: triangles with at least one light vertex */
+    int64_t heavy;            /* T_H: triangles with three heavy vertices */
+    int64_t m;                /* edges of the counted graph (m' after sampling) */
+    int64_t n_heavy;          /* |H| */
+    /* work statistics of the light phase (for throughput models) */
+    int64_t light_sources;    /* light vertices u with out-degree d+(u) >= 2 */
+    int64_t light_out_edges;  /* sum of d+(u) over those u */
+    int64_t wedges;           /* sum of C(d+(u), 2) over those u */
+    int64_t gather;           /* sum over those u and v in N+(u) of d+(v) */
+} tc_counts;
+
+/* Device allocator used for every internal buffer and graph.  alloc returns
+   NULL on failure (the call then fails with TC_ERR_OOM).  Passing NULL for
+   both restores the built-in caching pool.  Not thread-safe against
+   concurrent calls. */
+typedef void* (*tc_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*tc_free_fn)(void* ptr, void* stream, void* ctx);
+tc_status tc_set_allocator(tc_alloc_fn alloc, tc_free_fn free_, void* ctx);
+
+/* Build the simple undirected graph of the pairs (src[i], dst[i]), i < num_pairs
+   (section 4.1: duplicates and self-loops removed; section 4.2: sorted
+   neighbour lists).  src/dst are device pointers if on_device, else host
+   pointers (copied in).  They are borrowed for the call.  Ids outside [0,n)
+   give TC_ERR_INVALID.  *out receives a new handle. */
+tc_status tc_build_csr(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst,
+                       int32_t on_device, void* stream, tc_graph* out);
+
+/* Size queries.  Any output pointer may be NULL. */
+tc_status tc_graph_info(tc_graph g, int64_t* n, int64_t* m, int32_t* max_deg);
+
+/* Borrowed device pointers to the CSR (valid until tc_graph_free):
+   row_ptr int32[n+1], col int32[2m]. */
+tc_status tc_graph_csr(tc_graph g, const int32_t** row_ptr, const int32_t** col);
+
+/* Copy the CSR out into caller buffers: row_ptr[n+1], col[2m] and deg[n]
+   (any may be NULL), device pointers if on_device, else host pointers. */
+tc_status tc_graph_read(tc_graph g, int32_t* row_ptr, int32_t* col, int32_t* deg, int32_t on_device, void* stream);
+
+/* Edge sparsification (section 3.1): a new graph keeping each undirected edge
+   {u,v} iff (mix64(mix64(min<<32 | max) ^ mix64(seed ^ 0x54435F53414D504C)) >> 11)
+   < floor(p * 2^53), where mix64 is the SplitMix64 output function.  p must be
+   finite and in (0,1]. */
+tc_status tc_sample(tc_graph g, double p, uint64_t seed, void* stream, tc_graph* out_sampled);
+
+/* Exact triangle count of g with the light/heavy split (section 3.2; the
+   "Exact" columns of Table 2).  prm may be NULL (defaults). */
+tc_status tc_count_exact(tc_graph g, const tc_params* prm, void* stream, tc_counts* out);
+
+/* Sparsify-then-count estimate (section 3.1): for each seed s, T_s is the exact
+   count of the graph sampled with (p, s), and est_s = (double)T_s / ((p*p)*p).
+   num_seeds >= 1, 1 <= num_groups <= num_seeds, num_seeds % num_groups == 0.
+   mom_est receives the median of means of the group means (groups of
+   num_seeds/num_groups consecutive seeds; for an even number of groups the
+   mean of the two middle group sums, divided once).  per_seed[num_seeds],
+   per_seed_est[num_seeds] and mom_est may each be NULL. */
+tc_status tc_estimate(tc_graph g, double p, const uint64_t* seeds, int32_t num_seeds,
+                      int32_t num_groups, const tc_params* prm, void* stream,
+                      tc_counts* per_seed, double* per_seed_est, double* mom_est);
+
+/* Random-projection estimator (section 5.1) with Rademacher vectors: for
+   l < k, x_l[i] = +1 if bit (l & 63) of
+   mix64(mix64((l >> 6) << 32 | i) ^ mix64(seed ^ 0x52505F5452414345)) is 0, else -1;
+   q[l] = x_l^T A^3 x_l computed exactly in int64, and *tri_est = (sum_l q[l]
+   summed in 128-bit) / (6k).  q is a host array of k entries; tri_est may be
+   NULL.  TC_ERR_OVERFLOW if k * sum over directed edges (i,j) of deg_i * deg_j
+   could reach 2^63. */
+tc_status tc_rp_trace(tc_graph g, int32_t k, uint64_t seed, void* stream, int64_t* q, double* tri_est);
+
+/* Release a graph (NULL is ignored). */
+void tc_graph_free(tc_graph g);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* tc_last_error(void);
+
+/* ---- measurement hooks --------------------------------------------------- */
+
+/* When enabled, every kernel launch is bracketed by HIP events on its stream
+   and its duration accumulated under the kernel's name. */
+tc_status tc_profile_enable(int32_t on);
+tc_status tc_profile_reset(void);
+/* Accumulated milliseconds and launch count of a named kernel (0 if unseen). */
+tc_status tc_profile_read(const char* kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H_ */

@@ -1,0 +1,160 @@
+"""Degree-partitioned sampling triangle counter for one MI355X (gfx950).
+
+Thin Python binding over the C ABI of ``libtc.so`` (``include/tc.h``): it only
+marshals arguments.  Every step of the counting path runs in the library's
+HIP kernels; PyTorch supplies device memory for inputs and the stream.
+
+The method is Kolountzakis, Miller, Peng, Tsourakakis, "Efficient Triangle
+Counting in Large Graphs via Degree-based Vertex Partitioning"
+(arXiv:1011.0468): edge sparsification (section 3.1), light/heavy vertex
+partition (section 3.2), exact count rescaled by 1/p^3, and the random
+projection estimator of section 5.1.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _native
+from ._native import TcCounts, TcError, TcParams, check
+
+__all__ = ["Graph", "tc_build_csr", "tc_sample", "tc_count_exact", "tc_estimate", "tc_rp_trace",
+           "tc_graph_info", "tc_graph_read", "profile", "TcError"]
+
+
+def _stream_ptr(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    import torch
+    if torch.cuda.is_available():
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(0)
+
+
+def _params(heavy=(1, 1), tuned=False):
+    return TcParams(int(heavy[0]), int(heavy[1]), 1 if tuned else 0)
+
+
+class Graph:
+    """Owning wrapper of a ``tc_graph`` handle (freed with the object)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        return tc_graph_info(self)
+
+    def read(self, stream=None):
+        return tc_graph_read(self, stream)
+
+    def free(self):
+        if self._h and self._h.value:
+            _native.load().tc_graph_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def tc_build_csr(n, src, dst, stream=None):
+    """Simple undirected graph of the pairs (src[i], dst[i]).
+
+    ``src``/``dst``: int32 torch tensors (CUDA: read in place; CPU: copied in)
+    or numpy arrays (copied in)."""
+    L = _native.load()
+    keep = []
+    if isinstance(src, np.ndarray):
+        s = np.ascontiguousarray(src, dtype=np.int32)
+        d = np.ascontiguousarray(dst, dtype=np.int32)
+        keep += [s, d]
+        ps, pd, on_dev = s.ctypes.data, d.ctypes.data, 0
+    else:
+        import torch
+        s = src.to(torch.int32).contiguous()
+        d = dst.to(torch.int32).contiguous()
+        keep += [s, d]
+        ps, pd, on_dev = s.data_ptr(), d.data_ptr(), 1 if s.is_cuda else 0
+    if len(s) != len(d):
+        raise ValueError("src and dst differ in length")
+    out = ctypes.c_void_p(0)
+    check(L.tc_build_csr(int(n), len(s), ctypes.c_void_p(ps), ctypes.c_void_p(pd), on_dev, _stream_ptr(stream),
+                         ctypes.byref(out)))
+    return Graph(out.value)
+
+
+def tc_graph_info(g):
+    n, m, md = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    check(_native.load().tc_graph_info(g.handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(md)))
+    return dict(n=n.value, m=m.value, max_deg=md.value)
+
+
+def tc_graph_read(g, stream=None):
+    """(row_ptr, col, deg) as host numpy int32 arrays."""
+    inf = tc_graph_info(g)
+    rp = np.empty(inf["n"] + 1, np.int32)
+    col = np.empty(max(2 * inf["m"], 1), np.int32)
+    deg = np.empty(max(inf["n"], 1), np.int32)
+    check(_native.load().tc_graph_read(g.handle, ctypes.c_void_p(rp.ctypes.data), ctypes.c_void_p(col.ctypes.data),
+                                       ctypes.c_void_p(deg.ctypes.data), 0, _stream_ptr(stream)))
+    return rp, col[: 2 * inf["m"]], deg[: inf["n"]]
+
+
+def tc_sample(g, p, seed, stream=None):
+    out = ctypes.c_void_p(0)
+    check(_native.load().tc_sample(g.handle, float(p), int(seed) & (2 ** 64 - 1), _stream_ptr(stream),
+                                   ctypes.byref(out)))
+    return Graph(out.value)
+
+
+def tc_count_exact(g, heavy=(1, 1), tuned=False, stream=None):
+    c = TcCounts()
+    prm = _params(heavy, tuned)
+    check(_native.load().tc_count_exact(g.handle, ctypes.byref(prm), _stream_ptr(stream), ctypes.byref(c)))
+    return c.as_dict()
+
+
+def tc_estimate(g, p, seeds, num_groups=1, heavy=(1, 1), tuned=False, stream=None):
+    """Returns (per_seed counts list, per_seed estimates list, median of means)."""
+    seeds = [int(s) & (2 ** 64 - 1) for s in seeds]
+    S = len(seeds)
+    arr = (ctypes.c_uint64 * S)(*seeds)
+    per = (TcCounts * S)()
+    ests = (ctypes.c_double * S)()
+    mom = ctypes.c_double(0.0)
+    prm = _params(heavy, tuned)
+    check(_native.load().tc_estimate(g.handle, float(p), arr, S, int(num_groups), ctypes.byref(prm),
+                                     _stream_ptr(stream), per, ests, ctypes.byref(mom)))
+    return [c.as_dict() for c in per], list(ests), mom.value
+
+
+def tc_rp_trace(g, k, seed, stream=None):
+    """(q int64[k] numpy array, triangle estimate)."""
+    q = np.zeros(k, np.int64)
+    est = ctypes.c_double(0.0)
+    check(_native.load().tc_rp_trace(g.handle, int(k), int(seed) & (2 ** 64 - 1), _stream_ptr(stream),
+                                     q.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(est)))
+    return q, est.value
+
+
+class profile:
+    """Launch timing collected by the library with HIP events on the launch stream."""
+
+    @staticmethod
+    def enable(on=True):
+        check(_native.load().tc_profile_enable(1 if on else 0))
+
+    @staticmethod
+    def reset():
+        check(_native.load().tc_profile_reset())
+
+    @staticmethod
+    def read(kernel):
+        ms, cnt = ctypes.c_double(0.0), ctypes.c_int64(0)
+        check(_native.load().tc_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value

@@ -1,0 +1,86 @@
+"""ctypes declarations of libtc.so (the C ABI in include/tc.h).
+
+The library is built in-tree by ``paper_1011_0468_amd.build``; importing this
+module fails loudly if it is missing.  There is no fallback implementation.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libtc.so")
+
+TC_OK, TC_ERR_INVALID, TC_ERR_OOM, TC_ERR_DEVICE, TC_ERR_OVERFLOW, TC_ERR_BUDGET = range(6)
+STATUS_NAMES = {0: "TC_OK", 1: "TC_ERR_INVALID", 2: "TC_ERR_OOM", 3: "TC_ERR_DEVICE",
+                4: "TC_ERR_OVERFLOW", 5: "TC_ERR_BUDGET"}
+
+
+class TcParams(ctypes.Structure):
+    _fields_ = [("heavy_num", ctypes.c_int32), ("heavy_den", ctypes.c_int32), ("use_tuned", ctypes.c_int32)]
+
+
+class TcCounts(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("triangles", "light", "heavy", "m", "n_heavy", "light_sources", "light_out_edges",
+                 "wedges", "gather")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class TcError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+# every symbol declared in include/tc.h
+EXPORTS = ["tc_set_allocator", "tc_build_csr", "tc_graph_info", "tc_graph_csr", "tc_graph_read", "tc_sample",
+           "tc_count_exact", "tc_estimate", "tc_rp_trace", "tc_graph_free", "tc_last_error",
+           "tc_profile_enable", "tc_profile_reset", "tc_profile_read"]
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO_PATH):
+        raise RuntimeError("libtc.so is not built (run __graft_entry__.build()); "
+                           "there is no fallback path")
+    L = ctypes.CDLL(SO_PATH)
+    vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    P = ctypes.POINTER
+    sigs = {
+        "tc_set_allocator": [ALLOC_FN, FREE_FN, vp],
+        "tc_build_csr": [i64, i64, vp, vp, i32, vp, P(vp)],
+        "tc_graph_info": [vp, P(i64), P(i64), P(i32)],
+        "tc_graph_csr": [vp, P(vp), P(vp)],
+        "tc_graph_read": [vp, vp, vp, vp, i32, vp],
+        "tc_sample": [vp, dbl, u64, vp, P(vp)],
+        "tc_count_exact": [vp, P(TcParams), vp, P(TcCounts)],
+        "tc_estimate": [vp, dbl, P(u64), i32, i32, P(TcParams), vp, P(TcCounts), P(dbl), P(dbl)],
+        "tc_rp_trace": [vp, i32, u64, vp, P(i64), P(dbl)],
+        "tc_profile_enable": [i32],
+        "tc_profile_reset": [],
+        "tc_profile_read": [ctypes.c_char_p, P(dbl), P(i64)],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.tc_graph_free.argtypes = [vp]
+    L.tc_graph_free.restype = None
+    L.tc_last_error.argtypes = []
+    L.tc_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != TC_OK:
+        msg = load().tc_last_error().decode(errors="replace")
+        raise TcError(status, msg)

@@ -1,0 +1,167 @@
+// Internal declarations shared by the HIP translation units of libtc.
+// Device code targets gfx950 only: wave64, 160 KB LDS per CU, int8 MFMA.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+
+#include "../../include/tc.h"
+
+namespace tc {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Host side: status plumbing
+// ---------------------------------------------------------------------------
+
+struct Error {
+    tc_status status;
+    std::string msg;
+};
+
+// Thrown inside the library only; every extern "C" entry point catches it.
+[[noreturn]] void fail(tc_status st, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+
+// Device allocation through the installed allocator (throws TC_ERR_OOM).
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// RAII device buffer.
+template <typename T>
+struct DevBuf {
+    T* ptr = nullptr;
+    size_t count = 0;
+    hipStream_t stream = nullptr;
+    DevBuf() = default;
+    DevBuf(size_t n, hipStream_t s) { reset(n, s); }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), count(o.count), stream(o.stream) { o.ptr = nullptr; o.count = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) { release(); ptr = o.ptr; count = o.count; stream = o.stream; o.ptr = nullptr; o.count = 0; }
+        return *this;
+    }
+    void reset(size_t n, hipStream_t s) {
+        release();
+        stream = s;
+        count = n;
+        ptr = static_cast<T*>(dev_alloc((n ? n : 1) * sizeof(T), s));
+    }
+    void release() {
+        if (ptr) dev_free(ptr, stream);
+        ptr = nullptr;
+        count = 0;
+    }
+    T* get() const { return ptr; }
+};
+
+// ---------------------------------------------------------------------------
+// Profiling of launches (events on the launch stream)
+// ---------------------------------------------------------------------------
+
+struct LaunchScope {
+    const char* name;
+    hipStream_t stream;
+    void* ev0 = nullptr;
+    LaunchScope(const char* n, hipStream_t s);
+    ~LaunchScope();
+};
+
+// Resolve recorded events into per-kernel totals (call after the stream is synchronised).
+void profile_collect();
+
+#define TC_LAUNCH(name, kernel, grid, block, shmem, stream, ...)                           \
+    do {                                                                                    \
+        ::tc::LaunchScope _tc_scope((name), (stream));                                      \
+        hipLaunchKernelGGL(kernel, (grid), (block), (shmem), (stream), __VA_ARGS__);        \
+        ::tc::check_hip(hipGetLastError(), (name));                                         \
+    } while (0)
+
+inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Graph handle
+// ---------------------------------------------------------------------------
+
+}  // namespace tc
+
+struct tc_graph_s {
+    int64_t n = 0;
+    int64_t m = 0;            // undirected edges
+    int32_t max_deg = 0;
+    int32_t* row_ptr = nullptr;   // [n+1]
+    int32_t* col = nullptr;       // [2m]
+    int32_t* src = nullptr;       // [2m] row index of each CSR entry
+    int32_t* deg = nullptr;       // [n]
+    hipStream_t home = nullptr;   // stream the buffers were allocated on
+};
+
+namespace tc {
+
+// ---------------------------------------------------------------------------
+// Device-wide primitives (tc_scan.hip)
+// ---------------------------------------------------------------------------
+
+// Exclusive scan of in[0..N) into out[0..N], out[N] = total.  In-place allowed.
+void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t N, hipStream_t s);
+void fill_i32(int32_t* p, int32_t v, int64_t N, hipStream_t s);
+void fill_i64(int64_t* p, int64_t v, int64_t N, hipStream_t s);
+void fill_u8(uint8_t* p, uint8_t v, int64_t N, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// CSR build (tc_csr.hip)
+// ---------------------------------------------------------------------------
+
+// Build into g (allocations through dev_alloc).  Returns 0 or 1 if an id is out of range.
+int build_csr(int64_t n, int64_t num_pairs, const int32_t* src_dev, const int32_t* dst_dev,
+              hipStream_t s, tc_graph_s* g);
+
+// ---------------------------------------------------------------------------
+// Sampling (tc_sample.hip)
+// ---------------------------------------------------------------------------
+
+uint64_t keep_threshold(double p);
+uint64_t sample_salt(uint64_t seed);
+
+// keep bits (one uint64 per 64 CSR entries) and per-word popcounts
+void sample_keep_bits(const tc_graph_s* g, uint64_t salt, uint64_t thr, uint64_t* bits, int32_t* wcnt,
+                      hipStream_t s);
+// rank of CSR position e among kept entries, for every row start: rp_out[x] (x in [0,n])
+void positions_at_rows(const int32_t* row_ptr, int64_t n, int64_t E2, const uint64_t* bits,
+                       const int32_t* wpre, int32_t* rp_out, int32_t* deg_out, hipStream_t s);
+// compaction of kept entries (col and src)
+void compact_kept(const int32_t* col, const int32_t* src, int64_t E2, const uint64_t* bits,
+                  const int32_t* wpre, int32_t* col_out, int32_t* src_out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Counting core (tc_count.hip)
+// ---------------------------------------------------------------------------
+
+struct CountConfig {
+    int32_t heavy_num = 1, heavy_den = 1;
+    int32_t small_dmax = 256;        // light sources with d+ <= small_dmax use a wave each
+    int32_t chunk_small = 16384;     // gather positions per small item
+    int32_t chunk_large = 65536;     // gather positions per large item
+    int32_t light_blocks_per_cu = 8; // persistent grid of the small-bin kernel
+};
+
+// Exact count of the graph, or of its copy sampled with (thr, salt) if sampled != 0.
+void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
+                hipStream_t s, tc_counts* out);
+
+// ---------------------------------------------------------------------------
+// Random projection (tc_rp.hip)
+// ---------------------------------------------------------------------------
+
+void rp_trace(const tc_graph_s* g, int32_t k, uint64_t seed, hipStream_t s, int64_t* q_host);
+
+// Autotuned parameters for a graph signature (tc_tune.cpp)
+CountConfig tuned_config(const tc_graph_s* g, int sampled, double p, const CountConfig& base);
+
+}  // namespace tc
