@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the sampling triangle counter on one MI355X.
+
+Workload (default): R-MAT scale 22, edge factor 16 (a/b/c = .57/.19/.19, no
+noise, seeded relabelling, generator seed 1), symmetrised and cleaned into an
+int32 CSR that stays resident in HBM.  One step is the whole counting path at
+the four operating points of that workload: the exact count (p = 1) and the
+sparsify-then-count estimates at p = 0.5, 0.1 and 0.05 with seed 0 (each:
+hash coin, degree orientation, light/heavy split, light wedge closure, heavy
+int8-MFMA block, rescale).  The metric is sampled-graph edges per second: the
+edges of the four counted graphs (m, m'_0.5, m'_0.1, m'_0.05) divided by the
+step time.  The CSR build is timed separately (the paper also leaves the
+conversion to its sorted-list format out of its timings, section 4.2).
+
+Prints one JSON line.  Only one GPU is supported.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DOMINANT = ("light_small", "light_large")
+
+
+def _light_model_bytes(c, large):
+    """Bytes the light closure must read (list model): staging N+(u) (4 B per
+    out-edge), every gathered N+(v) entry (4 B), and a row-offset pair (8 B)
+    per source and per out-neighbour."""
+    if large:
+        src, out, gat = c["light_sources_large"], c["light_out_edges_large"], c["gather_large"]
+    else:
+        src = c["light_sources"] - c["light_sources_large"]
+        out = c["light_out_edges"] - c["light_out_edges_large"]
+        gat = c["gather"] - c["gather_large"]
+    return 4 * out + 4 * gat + 8 * (src + out)
+
+
+def _source_sha():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1011_0468_amd", "csrc", "tc_count.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("source_sha") != _source_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(workload, ps, seed, gpu_counts):
+    """The oracle (single-threaded C) on a bounded sample of the same workload."""
+    import oracle
+    import synth
+    g = oracle.normalise(*synth.workload(workload))
+    edges, secs = 0, 0.0
+    parity = True
+    for p in ps:
+        t = time.perf_counter()
+        gp = oracle.sample(g, p, seed)
+        r = oracle.count_split(gp, 1, 1)
+        secs += time.perf_counter() - t
+        edges += r["m"]
+        if p in gpu_counts and gpu_counts[p] != r["triangles"]:
+            parity = False
+    return {"value": edges / secs, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "%s, p in %s, seed %d: oracle sample + exact split count of each sampled graph "
+                      "(%.1f s single-threaded; the p=1 and p=0.5 legs are left out for time)"
+                      % (workload, list(ps), seed, secs),
+            "parity_with_gpu": parity}
+
+
+def copy_probe(mib):
+    """A plain device copy of known size, for scaling rocprofv3 byte counters."""
+    import torch
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": a.numel() * 4, "launches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22")
+    ap.add_argument("--ps", default="1,0.5,0.1,0.05")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the counting path has no multi-GPU mode "
+              "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+        return
+
+    import synth
+    import paper_1011_0468_amd as tc
+
+    ps = [float(x) for x in args.ps.split(",")]
+    n, s, d = synth.workload(args.workload)
+    src = torch.from_numpy(s).cuda()
+    dst = torch.from_numpy(d).cuda()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g = tc.tc_build_csr(n, src, dst)
+    torch.cuda.synchronize()
+    csr_ms = (time.perf_counter() - t) * 1e3
+    del src, dst
+    info = g.info()
+
+    def step():
+        out = []
+        for p in ps:
+            if p == 1.0:
+                c = tc.tc_count_exact(g)
+                c["est"] = float(c["triangles"])
+            else:
+                per, ests, _ = tc.tc_estimate(g, p, [args.seed])
+                c = per[0]
+                c["est"] = ests[0]
+            c["p"] = p
+            out.append(c)
+        return out
+
+    for _ in range(args.warmup):
+        step()
+    # per-call breakdown (untimed): wall time of each operating point
+    per_call_ms = []
+    for p in ps:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if p == 1.0:
+            tc.tc_count_exact(g)
+        else:
+            tc.tc_estimate(g, p, [args.seed])
+        torch.cuda.synchronize()
+        per_call_ms.append(round((time.perf_counter() - t) * 1e3, 3))
+
+    tc.profile.select(list(DOMINANT))
+    tc.profile.reset()
+    tc.profile.enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tc.profile.enable(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    edges = sum(c["m"] for c in res)
+    value = edges / (ms_per_step / 1e3)
+
+    # roofline of the dominant kernel: algorithmic bytes / measured launch time
+    kern = {}
+    for name in DOMINANT:
+        ms_tot, launches = tc.profile.read(name)
+        large = name == "light_large"
+        model = sum(_light_model_bytes(c, large) for c in res) * args.steps
+        kern[name] = (ms_tot, launches, model)
+    dom = max(DOMINANT, key=lambda k: kern[k][0])
+    ms_tot, launches, model = kern[dom]
+    achieved = (model / (ms_tot / 1e3)) / 1e9 if ms_tot > 0 else 0.0
+    traffic = _traffic(dom, args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "avg_launch_ms": round(ms_tot / max(launches, 1), 4), "launches": launches,
+                "model_bytes_per_launch": int(model / max(launches, 1))}
+
+    line = {
+        "metric": "sampled-graph edges/sec (1 MI355X) at R-MAT s22",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": info["n"], "m": info["m"], "ps": ps, "seed": args.seed,
+                   "split": "light iff deg <= sqrt(m')", "csr": "int32, resident in HBM"},
+        "roofline": roofline,
+        "csr_build_ms": round(csr_ms, 2),
+        "per_call_ms": dict(zip([str(p) for p in ps], per_call_ms)),
+        "results": [{k: c[k] for k in ("p", "m", "triangles", "light", "heavy", "n_heavy", "est")} for c in res],
+    }
+    if not args.no_cpu_baseline:
+        gc = {c["p"]: c["triangles"] for c in res}
+        line["cpu_baseline"] = cpu_baseline(args.workload, [p for p in ps if p <= 0.1], args.seed, gc)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -74,6 +74,11 @@ typedef struct {
     int64_t light_out_edges;  /* sum of d+(u) over those u */
     int64_t wedges;           /* sum of C(d+(u), 2) over those u */
     int64_t gather;           /* sum over those u and v in N+(u) of d+(v) */
+    /* the share of the three sums above handled by the block-per-source kernel
+       (sources with large d+); the rest is handled one wave per source */
+    int64_t light_sources_large;
+    int64_t light_out_edges_large;
+    int64_t gather_large;
 } tc_counts;
 
 /* Device allocator used for every internal buffer and graph.  alloc returns
@@ -144,6 +149,9 @@ const char* tc_last_error(void);
 /* When enabled, every kernel launch is bracketed by HIP events on its stream
    and its duration accumulated under the kernel's name. */
 tc_status tc_profile_enable(int32_t on);
+/* Restrict profiling to the kernels named in a comma-separated list (NULL or
+   "" = every kernel). */
+tc_status tc_profile_select(const char* names);
 tc_status tc_profile_reset(void);
 /* Accumulated milliseconds and launch count of a named kernel (0 if unseen). */
 tc_status tc_profile_read(const char* kernel, double* total_ms, int64_t* launches);

@@ -150,6 +150,12 @@ class profile:
         check(_native.load().tc_profile_enable(1 if on else 0))
 
     @staticmethod
+    def select(names=None):
+        """Restrict profiling to these kernel names (None: all)."""
+        arg = None if not names else ",".join(names).encode()
+        check(_native.load().tc_profile_select(arg))
+
+    @staticmethod
     def reset():
         check(_native.load().tc_profile_reset())
 

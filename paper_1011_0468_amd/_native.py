@@ -21,7 +21,7 @@ class TcParams(ctypes.Structure):
 class TcCounts(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("triangles", "light", "heavy", "m", "n_heavy", "light_sources", "light_out_edges",
-                 "wedges", "gather")]
+                 "wedges", "gather", "light_sources_large", "light_out_edges_large", "gather_large")]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -39,7 +39,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 # every symbol declared in include/tc.h
 EXPORTS = ["tc_set_allocator", "tc_build_csr", "tc_graph_info", "tc_graph_csr", "tc_graph_read", "tc_sample",
            "tc_count_exact", "tc_estimate", "tc_rp_trace", "tc_graph_free", "tc_last_error",
-           "tc_profile_enable", "tc_profile_reset", "tc_profile_read"]
+           "tc_profile_enable", "tc_profile_select", "tc_profile_reset", "tc_profile_read"]
 
 _lib = None
 
@@ -66,6 +66,7 @@ def load():
         "tc_rp_trace": [vp, i32, u64, vp, P(i64), P(dbl)],
         "tc_profile_enable": [i32],
         "tc_profile_reset": [],
+        "tc_profile_select": [ctypes.c_char_p],
         "tc_profile_read": [ctypes.c_char_p, P(dbl), P(i64)],
     }
     for name, args in sigs.items():

@@ -151,6 +151,14 @@ bool g_prof_on = false;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_event_pool;
 std::map<std::string, std::pair<double, int64_t>> g_prof;
+std::vector<std::string> g_prof_names;  // empty: profile every kernel
+
+bool selected(const char* name) {
+    if (g_prof_names.empty()) return true;
+    for (auto& s : g_prof_names)
+        if (s == name) return true;
+    return false;
+}
 
 hipEvent_t take_event() {
     if (!g_event_pool.empty()) {
@@ -167,7 +175,7 @@ hipEvent_t take_event() {
 
 LaunchScope::LaunchScope(const char* n, hipStream_t s) : name(n), stream(s) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!g_prof_on || !selected(n)) return;
     hipEvent_t e = take_event();
     check_hip(hipEventRecord(e, s), "event record");
     ev0 = (void*)e;
@@ -480,6 +488,24 @@ tc_status tc_profile_enable(int32_t on) {
     return guarded([&] {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         g_prof_on = on != 0;
+    });
+}
+
+tc_status tc_profile_select(const char* names) {
+    return guarded([&] {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_names.clear();
+        if (!names) return;
+        std::string cur;
+        for (const char* c = names;; ++c) {
+            if (*c == ',' || *c == 0) {
+                if (!cur.empty()) g_prof_names.push_back(cur);
+                cur.clear();
+                if (*c == 0) break;
+            } else {
+                cur.push_back(*c);
+            }
+        }
     });
 }
 

@@ -26,7 +26,9 @@ namespace tc {
 
 namespace {
 
-enum Acc { kTL = 0, kTH = 1, kLightSources = 2, kLightOut = 3, kWedges = 4, kGather = 5, kDmaxLarge = 6, kAccN = 8 };
+enum Acc {
+    kTL = 0, kTH, kLightSources, kLightOut, kWedges, kGather, kDmaxLarge, kSrcLarge, kOutLarge, kGatherLarge, kAccN
+};
 
 unsigned grid_for(int64_t N, int threads) {
     unsigned b = ceil_div(N, threads);
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
                                                    int32_t* __restrict__ heavy, int32_t* __restrict__ nsm,
                                                    int32_t* __restrict__ nlg, int64_t* __restrict__ acc) {
     const int64_t mp = mp_dev[0];
-    int64_t ls = 0, lo = 0, wd = 0, ga = 0, dmax = 0;
+    int64_t ls = 0, lo = 0, wd = 0, ga = 0, dmax = 0, lsL = 0, loL = 0, gaL = 0;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t dg = degp[x];
         const int32_t dp = dplus[x];
@@ -150,19 +152,29 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
             ga += w;
             if (w > 0) {
                 if (dp <= small_dmax) cs = (int32_t)((w + chunk_s - 1) / chunk_s);
-                else { cl = (int32_t)((w + chunk_l - 1) / chunk_l); dmax = dp > dmax ? dp : dmax; }
+                else {
+                    cl = (int32_t)((w + chunk_l - 1) / chunk_l);
+                    dmax = dp > dmax ? dp : dmax;
+                    lsL += 1;
+                    loL += dp;
+                    gaL += w;
+                }
             }
         }
         nsm[x] = cs;
         nlg[x] = cl;
     }
     ls = wave_sum(ls); lo = wave_sum(lo); wd = wave_sum(wd); ga = wave_sum(ga); dmax = wave_max(dmax);
+    lsL = wave_sum(lsL); loL = wave_sum(loL); gaL = wave_sum(gaL);
     if (__lane_id() == 0) {
         if (ls) atomicAdd((unsigned long long*)&acc[kLightSources], (unsigned long long)ls);
         if (lo) atomicAdd((unsigned long long*)&acc[kLightOut], (unsigned long long)lo);
         if (wd) atomicAdd((unsigned long long*)&acc[kWedges], (unsigned long long)wd);
         if (ga) atomicAdd((unsigned long long*)&acc[kGather], (unsigned long long)ga);
         if (dmax) atomicMax((unsigned long long*)&acc[kDmaxLarge], (unsigned long long)dmax);
+        if (lsL) atomicAdd((unsigned long long*)&acc[kSrcLarge], (unsigned long long)lsL);
+        if (loL) atomicAdd((unsigned long long*)&acc[kOutLarge], (unsigned long long)loL);
+        if (gaL) atomicAdd((unsigned long long*)&acc[kGatherLarge], (unsigned long long)gaL);
     }
 }
 
@@ -572,6 +584,9 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
     res.light_out_edges = hacc[kLightOut];
     res.wedges = hacc[kWedges];
     res.gather = hacc[kGather];
+    res.light_sources_large = hacc[kSrcLarge];
+    res.light_out_edges_large = hacc[kOutLarge];
+    res.gather_large = hacc[kGatherLarge];
     *out = res;
 }
 

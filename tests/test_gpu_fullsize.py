@@ -1,0 +1,74 @@
+"""Full-size parity on the R-MAT scale-22 workload, in the launch
+configuration the benchmark times: the device CSR against the oracle's
+normalised graph, the sampled CSR at p = 0.1 against the oracle's sample, and
+the counts at p in {1, 0.5, 0.1, 0.05} (seed 0) against the oracle values
+stored in tests/golden/rmat22.json (written by tests/golden/make_golden.py)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _log(msg):
+    sys.stdout.write(msg + "\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rmat22(gpu):
+    import torch
+    n, s, d = synth.workload("rmat22")
+    _log("rmat22: building device CSR")
+    g = gpu.tc_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    return n, s, d, g
+
+
+def test_rmat22_csr_and_sample_match_oracle(gpu, rmat22):
+    n, s, d, g = rmat22
+    _log("rmat22: oracle normalise")
+    og = oracle.normalise(n, s, d)
+    rp, col, deg = gpu.tc_graph_read(g)
+    assert np.array_equal(rp.astype(np.int64), og[1])
+    assert np.array_equal(col, og[2])
+    _log("rmat22: sample p=0.1 seed 0")
+    gs = gpu.tc_sample(g, 0.1, 0)
+    rps, cols, _ = gpu.tc_graph_read(gs)
+    ogs = oracle.sample(og, 0.1, 0)
+    assert np.array_equal(rps.astype(np.int64), ogs[1])
+    assert np.array_equal(cols, ogs[2])
+
+
+def test_rmat22_counts_match_golden(gpu, rmat22):
+    n, s, d, g = rmat22
+    gold = json.load(open(os.path.join(GOLDEN, "rmat22.json")))
+    for want in gold["counts"]:
+        p = want["p"]
+        _log("rmat22: count p=%g" % p)
+        if p == 1.0:
+            got = gpu.tc_count_exact(g)
+            est = float(got["triangles"])
+        else:
+            per, ests, _ = gpu.tc_estimate(g, p, [want["seed"]])
+            got, est = per[0], ests[0]
+        for k in ("triangles", "light", "heavy", "n_heavy", "m"):
+            assert got[k] == want[k], (p, k, got[k], want[k])
+        assert est == oracle.estimate(want["triangles"], p)
+
+
+def test_rmat22_split_invariance(gpu, rmat22):
+    n, s, d, g = rmat22
+    gold = json.load(open(os.path.join(GOLDEN, "rmat22.json")))
+    want = [c for c in gold["counts"] if c["p"] == 0.1][0]
+    for a, b in [(1, 2), (2, 1), (1, 4)]:
+        _log("rmat22: p=0.1 split %d/%d" % (a, b))
+        per, _, _ = gpu.tc_estimate(g, 0.1, [0], heavy=(a, b))
+        assert per[0]["triangles"] == want["triangles"]
