@@ -29,16 +29,11 @@ DOMINANT = ("light_small", "light_large")
 
 
 def _light_model_bytes(c, large):
-    """Bytes the light closure must read (list model): staging N+(u) (4 B per
-    out-edge), every gathered N+(v) entry (4 B), and a row-offset pair (8 B)
-    per source and per out-neighbour."""
-    if large:
-        src, out, gat = c["light_sources_large"], c["light_out_edges_large"], c["gather_large"]
-    else:
-        src = c["light_sources"] - c["light_sources_large"]
-        out = c["light_out_edges"] - c["light_out_edges_large"]
-        gat = c["gather"] - c["gather_large"]
-    return 4 * out + 4 * gat + 8 * (src + out)
+    """Bytes a light-closure kernel must read under the list model, as counted
+    by the library: per work item the anchor's row offsets and its staged
+    out-list (4 B per entry); per iterated entry the entry and the row offsets
+    of its list; per probe the streamed list entry (4 B)."""
+    return c["model_bytes_large"] if large else c["model_bytes_small"]
 
 
 def _source_sha():

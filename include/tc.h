@@ -71,14 +71,16 @@ typedef struct {
     int64_t n_heavy;          /* |H| */
     /* work statistics of the light phase (for throughput models) */
     int64_t light_sources;    /* light vertices u with out-degree d+(u) >= 2 */
-    int64_t light_out_edges;  /* sum of d+(u) over those u */
+    int64_t light_out_edges;  /* sum of d+(u) over those u (oriented pairs (u, v)) */
     int64_t wedges;           /* sum of C(d+(u), 2) over those u */
-    int64_t gather;           /* sum over those u and v in N+(u) of d+(v) */
-    /* the share of the three sums above handled by the block-per-source kernel
-       (sources with large d+); the rest is handled one wave per source */
-    int64_t light_sources_large;
-    int64_t light_out_edges_large;
-    int64_t gather_large;
+    int64_t gather;           /* sum over those pairs of d+(v) (list entries read if every pair
+                                 streamed N+(v)) */
+    int64_t probes;           /* list entries actually streamed and tested (each pair streams the
+                                 shorter of N+(u), N+(v), within the staging cap) */
+    int64_t items_small;      /* work items of the wave-per-item kernel */
+    int64_t items_large;      /* work items of the block-per-item kernel */
+    int64_t model_bytes_small;/* bytes the wave-per-item kernel must read (list model) */
+    int64_t model_bytes_large;/* bytes the block-per-item kernel must read (list model) */
 } tc_counts;
 
 /* Device allocator used for every internal buffer and graph.  alloc returns
@@ -137,6 +139,30 @@ tc_status tc_estimate(tc_graph g, double p, const uint64_t* seeds, int32_t num_s
    NULL.  TC_ERR_OVERFLOW if k * sum over directed edges (i,j) of deg_i * deg_j
    could reach 2^63. */
 tc_status tc_rp_trace(tc_graph g, int32_t k, uint64_t seed, void* stream, int64_t* q, double* tri_est);
+
+/* ---- autotuner ------------------------------------------------------------ */
+
+/* Launch parameters of the count (none of them changes T; the heavy multiplier
+   changes the reported light/heavy split). */
+typedef struct {
+    int32_t heavy_num, heavy_den; /* heavy iff heavy_den^2 deg^2 > heavy_num^2 m */
+    int32_t small_dmax;           /* anchors with out-degree <= this use one wave per item (1..256) */
+    int32_t vmajor_cap;           /* pairs (u,v) with d+(u) <= d+(v) <= cap are closed from v's side;
+                                     0 closes every pair from u's side */
+    int32_t blocks_per_cu;        /* persistent grid of the wave-per-item kernel (1..16) */
+} tc_tuning;
+
+/* Entries are keyed by the graph signature (n, m) and the operating point
+   (sampled or not, p); calls with tc_params.use_tuned = 1 use them.
+   tc_tune_get returns the stored entry, or the defaults if there is none. */
+tc_status tc_tune_set(tc_graph g, double p, const tc_tuning* t);
+tc_status tc_tune_get(tc_graph g, double p, tc_tuning* t);
+
+/* Time every candidate of a fixed grid (heavy multiplier in {1/2, 1, 2},
+   vmajor_cap in {0, 1024}, small_dmax in {128, 256}) on the graph sampled
+   with (p, seed), store the fastest and return it in *best (may be NULL).
+   Counts of all candidates must agree; TC_ERR_DEVICE otherwise. */
+tc_status tc_autotune(tc_graph g, double p, uint64_t seed, void* stream, tc_tuning* best);
 
 /* Release a graph (NULL is ignored). */
 void tc_graph_free(tc_graph g);

@@ -15,10 +15,10 @@ import ctypes
 import numpy as np
 
 from . import _native
-from ._native import TcCounts, TcError, TcParams, check
+from ._native import TcCounts, TcError, TcParams, TcTuning, check
 
 __all__ = ["Graph", "tc_build_csr", "tc_sample", "tc_count_exact", "tc_estimate", "tc_rp_trace",
-           "tc_graph_info", "tc_graph_read", "profile", "TcError"]
+           "tc_graph_info", "tc_graph_read", "tc_tune_set", "tc_tune_get", "tc_autotune", "profile", "TcError"]
 
 
 def _stream_ptr(stream):
@@ -140,6 +140,24 @@ def tc_rp_trace(g, k, seed, stream=None):
     check(_native.load().tc_rp_trace(g.handle, int(k), int(seed) & (2 ** 64 - 1), _stream_ptr(stream),
                                      q.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(est)))
     return q, est.value
+
+
+def tc_tune_set(g, p, heavy=(1, 1), small_dmax=256, vmajor_cap=1024, blocks_per_cu=8):
+    t = TcTuning(int(heavy[0]), int(heavy[1]), int(small_dmax), int(vmajor_cap), int(blocks_per_cu))
+    check(_native.load().tc_tune_set(g.handle, float(p), ctypes.byref(t)))
+
+
+def tc_tune_get(g, p):
+    t = TcTuning()
+    check(_native.load().tc_tune_get(g.handle, float(p), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def tc_autotune(g, p, seed=0, stream=None):
+    t = TcTuning()
+    check(_native.load().tc_autotune(g.handle, float(p), int(seed) & (2 ** 64 - 1), _stream_ptr(stream),
+                                     ctypes.byref(t)))
+    return t.as_dict()
 
 
 class profile:

@@ -21,7 +21,16 @@ class TcParams(ctypes.Structure):
 class TcCounts(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("triangles", "light", "heavy", "m", "n_heavy", "light_sources", "light_out_edges",
-                 "wedges", "gather", "light_sources_large", "light_out_edges_large", "gather_large")]
+                 "wedges", "gather", "probes", "items_small", "items_large", "model_bytes_small",
+                 "model_bytes_large")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class TcTuning(ctypes.Structure):
+    _fields_ = [("heavy_num", ctypes.c_int32), ("heavy_den", ctypes.c_int32), ("small_dmax", ctypes.c_int32),
+                ("vmajor_cap", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -38,7 +47,8 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 
 # every symbol declared in include/tc.h
 EXPORTS = ["tc_set_allocator", "tc_build_csr", "tc_graph_info", "tc_graph_csr", "tc_graph_read", "tc_sample",
-           "tc_count_exact", "tc_estimate", "tc_rp_trace", "tc_graph_free", "tc_last_error",
+           "tc_count_exact", "tc_estimate", "tc_rp_trace", "tc_tune_set", "tc_tune_get", "tc_autotune",
+           "tc_graph_free", "tc_last_error",
            "tc_profile_enable", "tc_profile_select", "tc_profile_reset", "tc_profile_read"]
 
 _lib = None
@@ -64,6 +74,9 @@ def load():
         "tc_count_exact": [vp, P(TcParams), vp, P(TcCounts)],
         "tc_estimate": [vp, dbl, P(u64), i32, i32, P(TcParams), vp, P(TcCounts), P(dbl), P(dbl)],
         "tc_rp_trace": [vp, i32, u64, vp, P(i64), P(dbl)],
+        "tc_tune_set": [vp, dbl, P(TcTuning)],
+        "tc_tune_get": [vp, dbl, P(TcTuning)],
+        "tc_autotune": [vp, dbl, u64, vp, P(TcTuning)],
         "tc_profile_enable": [i32],
         "tc_profile_reset": [],
         "tc_profile_select": [ctypes.c_char_p],

@@ -251,7 +251,7 @@ CountConfig config_from(const tc_params* prm, const tc_graph_s* g, int sampled, 
         if (prm->heavy_den < 1 || prm->heavy_num < 0) fail(TC_ERR_INVALID, "heavy_num must be >= 0 and heavy_den >= 1");
         c.heavy_num = prm->heavy_num;
         c.heavy_den = prm->heavy_den;
-        if (prm->use_tuned) c = tuned_config(g, sampled, p, c);
+        if (prm->use_tuned) c = tuned_config(g, sampled, p, c);  // the table's entry replaces the split too
     }
     return c;
 }
@@ -470,6 +470,56 @@ tc_status tc_rp_trace(tc_graph g, int32_t k, uint64_t seed, void* stream, int64_
         for (int32_t l = 0; l < k; ++l) tot += hq[(size_t)l];
         std::memcpy(q, hq.data(), sizeof(int64_t) * (size_t)k);
         if (tri_est) *tri_est = (double)tot / (6.0 * (double)k);
+    });
+}
+
+static CountConfig from_tuning(const tc_tuning* t) {
+    CountConfig c;
+    if (t->heavy_den < 1 || t->heavy_num < 0) fail(TC_ERR_INVALID, "heavy_num must be >= 0 and heavy_den >= 1");
+    if (t->small_dmax < 1 || t->small_dmax > 256) fail(TC_ERR_INVALID, "small_dmax must be in [1, 256]");
+    if (t->vmajor_cap < 0) fail(TC_ERR_INVALID, "vmajor_cap must be >= 0");
+    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 16) fail(TC_ERR_INVALID, "blocks_per_cu must be in [1, 16]");
+    c.heavy_num = t->heavy_num;
+    c.heavy_den = t->heavy_den;
+    c.small_dmax = t->small_dmax;
+    c.vmajor_cap = t->vmajor_cap;
+    c.light_blocks_per_cu = t->blocks_per_cu;
+    return c;
+}
+
+static void to_tuning(const CountConfig& c, tc_tuning* t) {
+    t->heavy_num = c.heavy_num;
+    t->heavy_den = c.heavy_den;
+    t->small_dmax = c.small_dmax;
+    t->vmajor_cap = c.vmajor_cap;
+    t->blocks_per_cu = c.light_blocks_per_cu;
+}
+
+tc_status tc_tune_set(tc_graph g, double p, const tc_tuning* t) {
+    return guarded([&] {
+        if (!g || !t) fail(TC_ERR_INVALID, "graph or tuning is NULL");
+        if (!p_valid(p)) fail(TC_ERR_INVALID, "p must be finite and in (0, 1]");
+        tune_store(g, p < 1.0 ? 1 : 0, p, from_tuning(t));
+    });
+}
+
+tc_status tc_tune_get(tc_graph g, double p, tc_tuning* t) {
+    return guarded([&] {
+        if (!g || !t) fail(TC_ERR_INVALID, "graph or tuning is NULL");
+        if (!p_valid(p)) fail(TC_ERR_INVALID, "p must be finite and in (0, 1]");
+        CountConfig c;
+        tune_lookup(g, p < 1.0 ? 1 : 0, p, &c);
+        to_tuning(c, t);
+    });
+}
+
+tc_status tc_autotune(tc_graph g, double p, uint64_t seed, void* stream, tc_tuning* best) {
+    return guarded([&] {
+        if (!g) fail(TC_ERR_INVALID, "graph is NULL");
+        if (!p_valid(p)) fail(TC_ERR_INVALID, "p must be finite and in (0, 1]");
+        const int sampled = p < 1.0 ? 1 : 0;
+        CountConfig c = autotune(g, sampled, p, keep_threshold(p), sample_salt(seed), (hipStream_t)stream);
+        if (best) to_tuning(c, best);
     });
 }
 

@@ -7,10 +7,12 @@
 //      rank above every light vertex, so a triangle whose lowest vertex is
 //      heavy has three heavy vertices;
 //   3. light phase: for every light u, the wedges of section 3.2 (pairs of
-//      out-neighbours) are closed by testing, for each v in N+(u), which
-//      members of N+(v) lie in N+(u).  N+(u) is staged once in an LDS hash
-//      set; the concatenation of the N+(v) lists is split into fixed-size
-//      chunks so that every work item has a bounded cost;
+//      out-neighbours) are closed by counting, for each v in N+(u), the
+//      common members of N+(u) and N+(v).  Only the third edge of a wedge
+//      needs a test (section 4.2); the test streams the shorter of the two
+//      lists through an LDS hash set of the other: pairs whose N+(u) is
+//      shorter are grouped by v (N+(v) staged once, the N+(u) of v's light
+//      in-neighbours streamed), the others by u;
 //   4. heavy phase: the <= 2 m^(1/2) heavy vertices, in rank order, form a
 //      strictly upper-triangular 0/1 matrix U; sum((U U) .* U) counts each
 //      all-heavy triangle once (the matrix-multiplication route of Alon,
@@ -27,7 +29,8 @@ namespace tc {
 namespace {
 
 enum Acc {
-    kTL = 0, kTH, kLightSources, kLightOut, kWedges, kGather, kDmaxLarge, kSrcLarge, kOutLarge, kGatherLarge, kAccN
+    kTL = 0, kTH, kLightSources, kLightOut, kWedges, kGather, kProbes, kDmaxLarge, kBytesSmall, kBytesLarge,
+    kItemsSmall, kItemsLarge, kAccN
 };
 
 unsigned grid_for(int64_t N, int threads) {
@@ -48,29 +51,40 @@ int num_cus() {
     return cus;
 }
 
+// Entries of an iterated list processed by one work item.
+constexpr int kJL = 256;
+
 // ---------------------------------------------------------------------------
 // orientation
 // ---------------------------------------------------------------------------
 
+// Per CSR entry (u, v) of a kept edge: "up" if (deg u, u) < (deg v, v), else
+// "down".  Each kept undirected edge has exactly one up entry (in the row of
+// its lower-ranked end) and one down entry (in the row of its higher end).
 __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__ src, const int32_t* __restrict__ col,
                                                       int64_t E2, const uint64_t* __restrict__ keep,
-                                                      const int32_t* __restrict__ degp, uint64_t* __restrict__ obits,
-                                                      int32_t* __restrict__ ocnt) {
+                                                      const int32_t* __restrict__ degp, uint64_t* __restrict__ ubits,
+                                                      int32_t* __restrict__ ucnt, uint64_t* __restrict__ dbits,
+                                                      int32_t* __restrict__ dcnt) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < E2; e0 += stride) {
         const int64_t e = e0 + threadIdx.x;
-        bool o = false;
+        bool up = false, dn = false;
         if (e < E2) {
             const bool k = keep ? ((keep[e >> 6] >> (e & 63)) & 1ull) : true;
             if (k) {
                 const int32_t u = src[e], v = col[e];
-                o = rank_below(degp[u], u, degp[v], v);
+                up = rank_below(degp[u], u, degp[v], v);
+                dn = !up;
             }
         }
-        const uint64_t b = ballot64(o);
+        const uint64_t bu = ballot64(up);
+        const uint64_t bd = ballot64(dn);
         if (__lane_id() == 0 && e < E2) {
-            obits[e >> 6] = b;
-            ocnt[e >> 6] = __popcll(b);
+            ubits[e >> 6] = bu;
+            ucnt[e >> 6] = __popcll(bu);
+            dbits[e >> 6] = bd;
+            dcnt[e >> 6] = __popcll(bd);
         }
     }
 }
@@ -81,6 +95,27 @@ __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__
 
 __device__ __forceinline__ bool is_heavy(int64_t deg, int64_t m, int32_t a, int32_t b) {
     return (int64_t)b * b * deg * deg > (int64_t)a * a * m;
+}
+
+// Pair (u, v), u light: closed from v's side ("v-major": stage N+(v), stream
+// N+(u)) when N+(u) is the shorter list and N+(v) fits the staging cap; else
+// from u's side (stage N+(u), stream N+(v)).
+__device__ __forceinline__ bool vmajor(int32_t du, int32_t dv, int32_t vcap) {
+    return du <= dv && dv <= vcap;
+}
+
+// per vertex: heavy flag and code = d+(x) if x is a light source (light, d+ >= 2), else 0
+__global__ void k_vertex_prep(int64_t n, const int32_t* __restrict__ degp, const int32_t* __restrict__ dplus,
+                              const int32_t* __restrict__ mp_dev, int32_t ha, int32_t hb, int32_t* __restrict__ heavy,
+                              int32_t* __restrict__ code) {
+    const int64_t mp = mp_dev[0];
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t dg = degp[x];
+        const bool hv = dg > 0 && is_heavy(dg, mp, ha, hb);
+        heavy[x] = hv ? 1 : 0;
+        const int32_t dp = dplus[x];
+        code[x] = (!hv && dp >= 2) ? dp : 0;
+    }
 }
 
 // Sum of `val` over the run of equal `key` that ends at this lane; true on the
@@ -103,87 +138,124 @@ __device__ __forceinline__ bool run_tail_sum(int32_t key, bool valid, int64_t va
     return tail;
 }
 
-// W[u] += d+(v) for oriented u -> v with u light and d+(u) >= 2
-__global__ void __launch_bounds__(256) k_work(const int32_t* __restrict__ srcO, const int32_t* __restrict__ colO,
-                                               const int32_t* __restrict__ degp,
-                                               const int32_t* __restrict__ dplus, const int32_t* __restrict__ mp_dev,
-                                               int32_t ha, int32_t hb, int64_t* __restrict__ W) {
-    const int64_t mp = mp_dev[0];  // oriented edges = m'; entries beyond it are unused
-    const int64_t mo = mp;
+// Work of the anchors.  Over up entries (u -> v, grouped by u):
+//   Wu[u] += d+(v) for u-major pairs; gather statistic += d+(v) for every pair.
+// Over down entries (row v, entry u, grouped by v):
+//   Wv[v] += d+(u) for v-major pairs.
+__global__ void __launch_bounds__(256) k_work(const int32_t* __restrict__ rowE, const int32_t* __restrict__ colE,
+                                               const int32_t* __restrict__ mp_dev, const int32_t* __restrict__ code,
+                                               const int32_t* __restrict__ dplus, int32_t vcap, int32_t down,
+                                               int64_t* __restrict__ W, int64_t* __restrict__ acc) {
+    const int64_t mo = mp_dev[0];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t gsum = 0;
     for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < mo; e0 += stride) {
         const int64_t e = e0 + threadIdx.x;
         bool valid = false;
-        int32_t u = -1;
+        int32_t key = -1;
         int64_t val = 0;
         if (e < mo) {
-            u = srcO[e];
-            if (dplus[u] >= 2 && !is_heavy(degp[u], mp, ha, hb)) {
-                valid = true;
-                val = dplus[colO[e]];
+            key = rowE[e];
+            const int32_t y = colE[e];
+            if (!down) {
+                const int32_t cu = code[key];
+                if (cu > 0) {
+                    const int32_t dv = dplus[y];
+                    gsum += dv;
+                    if (!vmajor(cu, dv, vcap)) { valid = true; val = dv; }
+                }
+            } else {
+                const int32_t cu = code[y];
+                if (cu > 0 && vmajor(cu, dplus[key], vcap)) { valid = true; val = cu; }
             }
         }
         int64_t sum;
-        const bool tail = run_tail_sum(valid ? u : -1, valid, val, &sum);
-        if (tail) atomicAdd((unsigned long long*)&W[u], (unsigned long long)sum);
+        const bool tail = run_tail_sum(valid ? key : -1, valid, val, &sum);
+        if (tail) atomicAdd((unsigned long long*)&W[key], (unsigned long long)sum);
     }
-}
-
-// per-vertex: heavy flag, item counts of the two light bins, statistics
-__global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __restrict__ degp,
-                                                   const int32_t* __restrict__ dplus, const int64_t* __restrict__ W,
-                                                   const int32_t* __restrict__ mp_dev, int32_t ha, int32_t hb,
-                                                   int32_t small_dmax, int32_t chunk_s, int32_t chunk_l,
-                                                   int32_t* __restrict__ heavy, int32_t* __restrict__ nsm,
-                                                   int32_t* __restrict__ nlg, int64_t* __restrict__ acc) {
-    const int64_t mp = mp_dev[0];
-    int64_t ls = 0, lo = 0, wd = 0, ga = 0, dmax = 0, lsL = 0, loL = 0, gaL = 0;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t dg = degp[x];
-        const int32_t dp = dplus[x];
-        const bool hv = dg > 0 && is_heavy(dg, mp, ha, hb);
-        heavy[x] = hv ? 1 : 0;
-        int32_t cs = 0, cl = 0;
-        if (!hv && dp >= 2) {
-            const int64_t w = W[x];
-            ls += 1;
-            lo += dp;
-            wd += (int64_t)dp * (dp - 1) / 2;
-            ga += w;
-            if (w > 0) {
-                if (dp <= small_dmax) cs = (int32_t)((w + chunk_s - 1) / chunk_s);
-                else {
-                    cl = (int32_t)((w + chunk_l - 1) / chunk_l);
-                    dmax = dp > dmax ? dp : dmax;
-                    lsL += 1;
-                    loL += dp;
-                    gaL += w;
-                }
-            }
+    if (!down) {
+        gsum = wave_sum(gsum);
+        __shared__ int64_t red[4];
+        if (__lane_id() == 0) red[threadIdx.x >> 6] = gsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int64_t t = red[0] + red[1] + red[2] + red[3];
+            if (t) atomicAdd((unsigned long long*)&acc[kGather], (unsigned long long)t);
         }
-        nsm[x] = cs;
-        nlg[x] = cl;
-    }
-    ls = wave_sum(ls); lo = wave_sum(lo); wd = wave_sum(wd); ga = wave_sum(ga); dmax = wave_max(dmax);
-    lsL = wave_sum(lsL); loL = wave_sum(loL); gaL = wave_sum(gaL);
-    if (__lane_id() == 0) {
-        if (ls) atomicAdd((unsigned long long*)&acc[kLightSources], (unsigned long long)ls);
-        if (lo) atomicAdd((unsigned long long*)&acc[kLightOut], (unsigned long long)lo);
-        if (wd) atomicAdd((unsigned long long*)&acc[kWedges], (unsigned long long)wd);
-        if (ga) atomicAdd((unsigned long long*)&acc[kGather], (unsigned long long)ga);
-        if (dmax) atomicMax((unsigned long long*)&acc[kDmaxLarge], (unsigned long long)dmax);
-        if (lsL) atomicAdd((unsigned long long*)&acc[kSrcLarge], (unsigned long long)lsL);
-        if (loL) atomicAdd((unsigned long long*)&acc[kOutLarge], (unsigned long long)loL);
-        if (gaL) atomicAdd((unsigned long long*)&acc[kGatherLarge], (unsigned long long)gaL);
     }
 }
 
-__global__ void k_items(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ base,
-                        int2* __restrict__ items) {
+__device__ __forceinline__ int32_t items_of(int64_t w, int32_t len) {
+    return w > 0 ? (len + kJL - 1) / kJL : 0;
+}
+
+// per vertex: item counts of the two bins (wave / block anchors), statistics
+// and the model bytes of each light kernel:
+//   per item: anchor row offsets (8 B) + staging N+(anchor) (4 B per entry);
+//   per iterated entry: the entry (4 B) + row offsets of its list (8 B)
+//   (+ 4 B code for down lists); per probe: the streamed entry (4 B).
+__global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __restrict__ code,
+                                                   const int32_t* __restrict__ dplus, const int32_t* __restrict__ dminus,
+                                                   const int64_t* __restrict__ Wu, const int64_t* __restrict__ Wv,
+                                                   int32_t small_dmax, int32_t* __restrict__ nsm,
+                                                   int32_t* __restrict__ nlg, int64_t* __restrict__ acc) {
+    int64_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sources, out, wedges, probes, bytes_s, bytes_l, items_s, items_l
+    int64_t dmax = 0;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = cnt[x];
-        const int32_t b = base[x];
-        for (int32_t i = 0; i < c; ++i) items[b + i] = make_int2((int32_t)x, i);
+        const int32_t c = code[x];
+        const int32_t dp = dplus[x];
+        if (c > 0) { st[0] += 1; st[1] += c; st[2] += (int64_t)c * (c - 1) / 2; }
+        const int64_t wu = Wu[x], wv = Wv[x];
+        const int32_t cu = items_of(wu, dp);
+        const int32_t cv = items_of(wv, dminus[x]);
+        const int64_t bytes = (int64_t)(cu + cv) * (8 + 4 * (int64_t)dp) + (wu > 0 ? 12 * (int64_t)dp : 0) +
+                              (wv > 0 ? 16 * (int64_t)dminus[x] : 0) + 4 * (wu + wv);
+        st[3] += wu + wv;
+        const bool small = dp <= small_dmax;
+        if (small) { nsm[x] = cu + cv; nlg[x] = 0; st[4] += bytes; st[6] += cu + cv; }
+        else {
+            nsm[x] = 0;
+            nlg[x] = cu + cv;
+            st[5] += bytes;
+            st[7] += cu + cv;
+            if (cu + cv > 0) dmax = dp > dmax ? dp : dmax;
+        }
+    }
+    __shared__ int64_t red[4][9];
+    const int wv_ = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) st[q] = wave_sum(st[q]);
+    dmax = wave_max(dmax);
+    if (__lane_id() == 0) {
+        for (int q = 0; q < 8; ++q) red[wv_][q] = st[q];
+        red[wv_][8] = dmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) {
+            for (int q = 0; q < 8; ++q) red[0][q] += red[w][q];
+            red[0][8] = red[w][8] > red[0][8] ? red[w][8] : red[0][8];
+        }
+        const int slot[8] = {kLightSources, kLightOut, kWedges, kProbes, kBytesSmall, kBytesLarge, kItemsSmall,
+                             kItemsLarge};
+        for (int q = 0; q < 8; ++q)
+            if (red[0][q]) atomicAdd((unsigned long long*)&acc[slot[q]], (unsigned long long)red[0][q]);
+        if (red[0][8]) atomicMax((unsigned long long*)&acc[kDmaxLarge], (unsigned long long)red[0][8]);
+    }
+}
+
+// items of anchor x: (x, r) for the u-major ranges r of N+(x), then (~x, r)
+// for the v-major ranges r of N-(x)
+__global__ void k_items(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ base,
+                        const int32_t* __restrict__ dplus, const int32_t* __restrict__ dminus,
+                        const int64_t* __restrict__ Wu, const int64_t* __restrict__ Wv, int2* __restrict__ items) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        if (cnt[x] == 0) continue;
+        int32_t b = base[x];
+        const int32_t cu = items_of(Wu[x], dplus[x]);
+        const int32_t cv = items_of(Wv[x], dminus[x]);
+        for (int32_t r = 0; r < cu; ++r) items[b++] = make_int2((int32_t)x, r);
+        for (int32_t r = 0; r < cv; ++r) items[b++] = make_int2(~(int32_t)x, r);
     }
 }
 
@@ -208,13 +280,16 @@ __global__ void k_info(const int32_t* mp, const int32_t* sb, const int32_t* lb, 
 // light closure
 // ---------------------------------------------------------------------------
 
+// multiplicative hash on the 24-bit multiplier (full-rate v_mul_u32_u24), with
+// the high id bits folded in first
 __device__ __forceinline__ uint32_t hslot(int32_t w, int lg) {
-    return ((uint32_t)w * 0x9E3779B1u) >> (32 - lg);
+    const uint32_t x = (uint32_t)w ^ ((uint32_t)w >> 21);
+    return __umul24(x, 0x9E3779u) >> (32 - lg);
 }
 
 __device__ __forceinline__ void hash_insert(int32_t* tab, int lg, int32_t v) {
     const uint32_t mask = (1u << lg) - 1;
-    uint32_t s = hslot(v, lg);
+    uint32_t s = hslot(v, lg) & mask;
     while (true) {
         const int32_t prev = atomicCAS(&tab[s], -1, v);
         if (prev == -1 || prev == v) break;
@@ -224,7 +299,7 @@ __device__ __forceinline__ void hash_insert(int32_t* tab, int lg, int32_t v) {
 
 __device__ __forceinline__ int hash_contains(const int32_t* tab, int lg, int32_t w) {
     const uint32_t mask = (1u << lg) - 1;
-    uint32_t s = hslot(w, lg);
+    uint32_t s = hslot(w, lg) & mask;
     while (true) {
         const int32_t k = tab[s];
         if (k == w) return 1;
@@ -249,125 +324,207 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave per item (u, chunk), persistent over items with a static stride.
-// LDS per wave: hash (2*DS slots), P (DS+1), S (DS).
+// Closure tests for positions [a, b) of the concatenated streamed lists:
+// position g lies in list j (P[j] <= g < P[j+1]) at offset g - P[j] of the
+// list starting at colO[S[j]].  Lists are streamed one after another in
+// super-strips of 64 * U positions: each lane issues U independent loads
+// before probing.  Only the first list is located by search.  Whole wave.
+template <int U>
+__device__ __forceinline__ int32_t close_range(const int32_t* P, const int32_t* S, int d, int32_t a, int32_t b,
+                                               const int32_t* __restrict__ colO, const int32_t* tab, int lg,
+                                               int lane) {
+    int32_t cnt = 0;
+    if (a >= b) return 0;
+    int j = find_list(P, d, a);
+    int32_t pos = a;
+    while (pos < b) {
+        const int32_t lend = min(P[j + 1], b);
+        const int32_t base = S[j] - P[j];
+        for (int32_t g0 = pos; g0 < lend; g0 += 64 * U) {
+            int32_t x[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int32_t g = g0 + lane + 64 * k;
+                x[k] = g < lend ? colO[base + g] : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (x[k] >= 0) cnt += hash_contains(tab, lg, x[k]);
+        }
+        pos = lend;
+        ++j;
+    }
+    return cnt;
+}
+
+// Insert N+(x) (d entries at colO[rs..]) into the hash set; NT threads, thread t.
+template <int NT>
+__device__ __forceinline__ void build_hash(int32_t rs, int32_t d, const int32_t* __restrict__ colO, int32_t* tab,
+                                           int lg, int t) {
+    constexpr int R = 4;
+    for (int j0 = 0; j0 < d; j0 += NT * R) {
+        int32_t v[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int j = j0 + t + NT * k;
+            v[k] = j < d ? colO[rs + j] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (v[k] >= 0) hash_insert(tab, lg, v[k]);
+    }
+}
+
+// Stage the iterated entries L[0..cnt) (cnt <= kJL): for entry y, the streamed
+// list is N+(y) (start S, prefix P of lengths) if the pair is closed from this
+// anchor, else an empty list.  kind_u: anchor x = u, entries y = v in N+(u);
+// else anchor x = v, entries y = u in N-(v).  Returns the total length.
+template <int NT>
+__device__ __forceinline__ int32_t stage_lists(const int32_t* __restrict__ L, int32_t cnt, bool kind_u, int32_t dx,
+                                               int32_t vcap, const int32_t* __restrict__ rpO,
+                                               const int32_t* __restrict__ code, int32_t* P, int32_t* S,
+                                               int32_t* red, int t) {
+    constexpr int R = kJL / NT > 0 ? (kJL + NT - 1) / NT : 1;
+    int32_t y[R], st[R], ln[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int j = t * R + k;  // consecutive entries per thread
+        y[k] = j < cnt ? L[j] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        st[k] = 0;
+        ln[k] = 0;
+        if (y[k] >= 0) {
+            st[k] = rpO[y[k]];
+            const int32_t en = rpO[y[k] + 1];
+            const int32_t dy = en - st[k];
+            bool take;
+            if (kind_u) take = !vmajor(dx, dy, vcap);
+            else { const int32_t cu = code[y[k]]; take = cu > 0 && vmajor(cu, dx, vcap); }
+            ln[k] = take ? dy : 0;
+        }
+    }
+    int32_t loc = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) loc += ln[k];
+    int32_t ex, tot;
+    if (NT == 64) {
+        const int32_t inc = wave_inclusive_sum(loc);
+        ex = inc - loc;
+        tot = __shfl(inc, 63, 64);
+    } else {
+        ex = block_exclusive_sum<NT>(loc, red, &tot);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int j = t * R + k;
+        if (j < cnt) {
+            S[j] = st[k];
+            ex += ln[k];
+            P[j + 1] = ex;
+        }
+    }
+    return tot;
+}
+
+// One wave per item, persistent over items with a static stride.  Item
+// (x, r): anchor x, kind u (x >= 0) or v (encoded ~x), entries r*kJL.. of the
+// iterated list.  LDS per wave: hash (2*DS slots), P (kJL+1), S (kJL).
 template <int DS>
 __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ items, int64_t n_items,
-                                                      const int32_t* __restrict__ rpO,
-                                                      const int32_t* __restrict__ colO, int32_t chunk,
+                                                      const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
+                                                      const int32_t* __restrict__ rpD, const int32_t* __restrict__ colD,
+                                                      const int32_t* __restrict__ code, int32_t vcap,
                                                       int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 2 * DS;
-    __shared__ int32_t lds[4][HS_MAX + 2 * DS + 1];
+    __shared__ int32_t lds[4][HS_MAX + 2 * kJL + 1];
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
     int32_t* tab = lds[w];
     int32_t* P = tab + HS_MAX;
-    int32_t* S = P + DS + 1;
+    int32_t* S = P + kJL + 1;
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
     int64_t total = 0;
     for (int64_t it = gw; it < n_items; it += nw) {
         const int2 item = items[it];
-        const int32_t u = item.x;
-        const int32_t rs = rpO[u];
-        const int32_t d = rpO[u + 1] - rs;
+        const bool kind_u = item.x >= 0;
+        const int32_t x = kind_u ? item.x : ~item.x;
+        const int32_t rs = rpO[x];
+        const int32_t d = rpO[x + 1] - rs;
+        const int32_t* L;
+        int32_t llen;
+        if (kind_u) { L = colO + rs; llen = d; }
+        else { const int32_t ds = rpD[x]; L = colD + ds; llen = rpD[x + 1] - ds; }
+        const int32_t j0 = item.y * kJL;
+        const int32_t cnt = min(kJL, llen - j0);
         int lg = 6;
         while ((1 << lg) < 2 * d) ++lg;
         const int hs = 1 << lg;
         for (int i = lane; i < hs; i += 64) tab[i] = -1;
         if (lane == 0) P[0] = 0;
         wave_lds_sync();
-        int32_t carry = 0;
-        for (int j0 = 0; j0 < d; j0 += 64) {
-            const int j = j0 + lane;
-            int32_t len = 0;
-            if (j < d) {
-                const int32_t v = colO[rs + j];
-                const int32_t st = rpO[v];
-                len = rpO[v + 1] - st;
-                S[j] = st;
-                hash_insert(tab, lg, v);
-            }
-            const int32_t inc = wave_inclusive_sum(len);
-            if (j < d) P[j + 1] = carry + inc;
-            carry += __shfl(inc, 63, 64);
-        }
+        build_hash<64>(rs, d, colO, tab, lg, lane);
+        const int32_t W = stage_lists<64>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, nullptr, lane);
         wave_lds_sync();
-        const int32_t g0 = item.y * chunk;
-        const int32_t g1 = min(g0 + chunk, carry);
-        int32_t cnt = 0;
-        for (int32_t gb = g0; gb < g1; gb += 64) {
-            const int32_t g = gb + lane;
-            if (g < g1) {
-                const int j = find_list(P, d, g);
-                const int32_t x = colO[S[j] + (g - P[j])];
-                cnt += hash_contains(tab, lg, x);
-            }
-        }
-        total += cnt;
+        total += close_range<4>(P, S, cnt, 0, W, colO, tab, lg, lane);
         wave_lds_sync();
     }
     total = wave_sum(total);
     if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTL], (unsigned long long)total);
 }
 
-// One block (256 threads) per item; N+(u) of any light size.  The hash set and
-// the list tables live in dynamic LDS, or in a global scratch slice per block
-// when they do not fit (out-degrees beyond the LDS capacity).
+// One block (4 waves) per item for anchors with large out-lists.  The hash
+// set and the list tables live in dynamic LDS, or in a global scratch slice per
+// block when they do not fit.  After staging, each wave closes a quarter of
+// the item's positions.
 __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ items, int64_t n_items,
-                                                      const int32_t* __restrict__ rpO,
-                                                      const int32_t* __restrict__ colO, int32_t chunk, int32_t dcap,
+                                                      const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
+                                                      const int32_t* __restrict__ rpD, const int32_t* __restrict__ colD,
+                                                      const int32_t* __restrict__ code, int32_t vcap, int32_t dcap,
                                                       int32_t* __restrict__ gscratch, int64_t* __restrict__ acc) {
     extern __shared__ int32_t dyn[];
     __shared__ int32_t red[5];
-    // layout: hash table (up to 2 * dcap slots, 4 * dcap reserved), P (dcap + 1), S (dcap)
-    int32_t* base = gscratch ? gscratch + (int64_t)blockIdx.x * (int64_t)(4 * dcap + 2 * dcap + 2) : dyn;
+    // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL)
+    const int64_t per_block = 2 * (int64_t)dcap + 2 * kJL + 1;
+    int32_t* base = gscratch ? gscratch + (int64_t)blockIdx.x * per_block : dyn;
     int32_t* tab = base;
-    int32_t* P = base + 4 * dcap;
-    int32_t* S = P + dcap + 1;
+    int32_t* P = base + 2 * dcap;
+    int32_t* S = P + kJL + 1;
     const int t = threadIdx.x;
+    const int w = t >> 6;
+    const int lane = __lane_id();
     int64_t total = 0;
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = items[it];
-        const int32_t u = item.x;
-        const int32_t rs = rpO[u];
-        const int32_t d = rpO[u + 1] - rs;
+        const bool kind_u = item.x >= 0;
+        const int32_t x = kind_u ? item.x : ~item.x;
+        const int32_t rs = rpO[x];
+        const int32_t d = rpO[x + 1] - rs;
+        const int32_t* L;
+        int32_t llen;
+        if (kind_u) { L = colO + rs; llen = d; }
+        else { const int32_t ds = rpD[x]; L = colD + ds; llen = rpD[x + 1] - ds; }
+        const int32_t j0 = item.y * kJL;
+        const int32_t cnt = min(kJL, llen - j0);
         int lg = 6;
         while ((1 << lg) < 2 * d) ++lg;
         const int hs = 1 << lg;
         for (int i = t; i < hs; i += 256) tab[i] = -1;
         if (t == 0) P[0] = 0;
         __syncthreads();
-        int32_t carry = 0;
-        for (int j0 = 0; j0 < d; j0 += 256) {
-            const int j = j0 + t;
-            int32_t len = 0;
-            if (j < d) {
-                const int32_t v = colO[rs + j];
-                const int32_t st = rpO[v];
-                len = rpO[v + 1] - st;
-                S[j] = st;
-                hash_insert(tab, lg, v);
-            }
-            int32_t tot;
-            const int32_t ex = block_exclusive_sum<256>(len, red, &tot);
-            if (j < d) P[j + 1] = carry + ex + len;
-            carry += tot;
-        }
+        build_hash<256>(rs, d, colO, tab, lg, t);
+        const int32_t W = stage_lists<256>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, red, t);
         __syncthreads();
-        const int32_t g0 = item.y * chunk;
-        const int32_t g1 = min(g0 + chunk, carry);
-        int32_t cnt = 0;
-        for (int32_t g = g0 + t; g < g1; g += 256) {
-            const int j = find_list(P, d, g);
-            const int32_t x = colO[S[j] + (g - P[j])];
-            cnt += hash_contains(tab, lg, x);
-        }
-        total += cnt;
+        const int32_t q = (W + 3) / 4;
+        const int32_t a = min(w * q, W);
+        const int32_t b = min(a + q, W);
+        total += close_range<4>(P, S, cnt, a, b, colO, tab, lg, lane);
         __syncthreads();
     }
     total = wave_sum(total);
-    if (__lane_id() == 0 && total) atomicAdd((unsigned long long*)&acc[kTL], (unsigned long long)total);
+    if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTL], (unsigned long long)total);
 }
 
 // ---------------------------------------------------------------------------
@@ -465,11 +622,12 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
         return;
     }
     const int64_t NW = (E2 + 63) / 64;
+    if (cfg.small_dmax > 256 || cfg.small_dmax < 1) fail(TC_ERR_INVALID, "small_dmax must be in [1, 256]");
 
     DevBuf<int64_t> acc(kAccN, s);
     fill_i64(acc.get(), 0, kAccN, s);
 
-    // 1. degrees of the counted graph
+    // 1. degrees of the counted graph (section 3.1 coin if sampled)
     DevBuf<uint64_t> keep;
     DevBuf<int32_t> kpre;
     DevBuf<int32_t> degp_buf;
@@ -484,29 +642,40 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
         degp = degp_buf.get();
     }
 
-    // 2. orientation by (deg, id): compacted out-lists N+(u)
-    DevBuf<uint64_t> obits(NW, s);
-    DevBuf<int32_t> opre(NW + 1, s);
+    // 2. orientation by (deg, id): compacted up lists N+(x) and down lists N-(x)
+    DevBuf<uint64_t> ubits(NW, s), dbits(NW, s);
+    DevBuf<int32_t> upre(NW + 1, s), dpre(NW + 1, s);
     TC_LAUNCH("orient_bits", k_orient_bits, dim3(grid_for(E2, 256)), dim3(256), 0, s, g->src, g->col, E2,
-              (const uint64_t*)keep.get(), degp, obits.get(), opre.get());
-    scan_exclusive_i32(opre.get(), opre.get(), NW, s);
-    const int32_t* mp_dev = opre.get() + NW;  // number of oriented edges = m'
-    DevBuf<int32_t> rpO(n + 1, s), dplus(n, s);
-    positions_at_rows(g->row_ptr, n, E2, obits.get(), opre.get(), rpO.get(), dplus.get(), s);
-    // m' <= m: size the oriented lists by m
-    DevBuf<int32_t> colO(g->m, s), srcO(g->m, s);
-    compact_kept(g->col, g->src, E2, obits.get(), opre.get(), colO.get(), srcO.get(), s);
+              (const uint64_t*)keep.get(), degp, ubits.get(), upre.get(), dbits.get(), dpre.get());
+    scan_exclusive_i32(upre.get(), upre.get(), NW, s);
+    scan_exclusive_i32(dpre.get(), dpre.get(), NW, s);
+    const int32_t* mp_dev = upre.get() + NW;  // number of up entries = m'
+    DevBuf<int32_t> rpO(n + 1, s), dplus(n, s), rpD(n + 1, s), dminus(n, s);
+    positions_at_rows(g->row_ptr, n, E2, ubits.get(), upre.get(), rpO.get(), dplus.get(), s);
+    positions_at_rows(g->row_ptr, n, E2, dbits.get(), dpre.get(), rpD.get(), dminus.get(), s);
+    // m' <= m: size the lists by m
+    DevBuf<int32_t> colO(g->m, s), srcO(g->m, s), colD(g->m, s), srcD(g->m, s);
+    compact_kept(g->col, g->src, E2, ubits.get(), upre.get(), colO.get(), srcO.get(), s);
+    compact_kept(g->col, g->src, E2, dbits.get(), dpre.get(), colD.get(), srcD.get(), s);
 
-    // 3. classification, light work per source, item lists
-    DevBuf<int64_t> W(n, s);
-    fill_i64(W.get(), 0, n, s);
-    TC_LAUNCH("work", k_work, dim3(grid_for(g->m, 256)), dim3(256), 0, s, (const int32_t*)srcO.get(),
-              (const int32_t*)colO.get(), degp, (const int32_t*)dplus.get(), mp_dev, cfg.heavy_num, cfg.heavy_den,
-              W.get());
-    DevBuf<int32_t> heavy(n + 1, s), nsm(n + 1, s), nlg(n + 1, s);
-    TC_LAUNCH("classify", k_classify, dim3(grid_for(n, 256)), dim3(256), 0, s, n, degp, (const int32_t*)dplus.get(),
-              (const int64_t*)W.get(), mp_dev, cfg.heavy_num, cfg.heavy_den, cfg.small_dmax, cfg.chunk_small,
-              cfg.chunk_large, heavy.get(), nsm.get(), nlg.get(), acc.get());
+    // 3. classification, anchor work, item lists
+    const int32_t vcap = cfg.vmajor_cap;
+    DevBuf<int32_t> heavy(n + 1, s), code(n, s);
+    TC_LAUNCH("vertex_prep", k_vertex_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, n, degp,
+              (const int32_t*)dplus.get(), mp_dev, cfg.heavy_num, cfg.heavy_den, heavy.get(), code.get());
+    DevBuf<int64_t> Wu(n, s), Wv(n, s);
+    fill_i64(Wu.get(), 0, n, s);
+    fill_i64(Wv.get(), 0, n, s);
+    const unsigned wgrid = std::min<unsigned>(grid_for(g->m, 256), 8192u);
+    TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcO.get(), (const int32_t*)colO.get(),
+              mp_dev, (const int32_t*)code.get(), (const int32_t*)dplus.get(), vcap, 0, Wu.get(), acc.get());
+    if (vcap > 0)
+        TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcD.get(), (const int32_t*)colD.get(),
+                  mp_dev, (const int32_t*)code.get(), (const int32_t*)dplus.get(), vcap, 1, Wv.get(), acc.get());
+    DevBuf<int32_t> nsm(n + 1, s), nlg(n + 1, s);
+    TC_LAUNCH("classify", k_classify, dim3(std::min<unsigned>(grid_for(n, 256), 2048u)), dim3(256), 0, s, n,
+              (const int32_t*)code.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
+              (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), cfg.small_dmax, nsm.get(), nlg.get(), acc.get());
     DevBuf<int32_t> sbase(n + 1, s), lbase(n + 1, s), hpos(n + 1, s);
     scan_exclusive_i32(nsm.get(), sbase.get(), n, s);
     scan_exclusive_i32(nlg.get(), lbase.get(), n, s);
@@ -523,33 +692,36 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
     if (n_small > 0) {
         DevBuf<int2> items(n_small, s);
         TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)nsm.get(),
-                  (const int32_t*)sbase.get(), items.get());
+                  (const int32_t*)sbase.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
+                  (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
         int64_t blocks = (int64_t)num_cus() * cfg.light_blocks_per_cu;
         const int64_t need = (n_small + 3) / 4;
         if (blocks > need) blocks = need;
         TC_LAUNCH("light_small", k_light_small<256>, dim3((unsigned)blocks), dim3(256), 0, s,
                   (const int2*)items.get(), n_small, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
-                  cfg.chunk_small, acc.get());
+                  (const int32_t*)rpD.get(), (const int32_t*)colD.get(), (const int32_t*)code.get(), vcap, acc.get());
     }
     if (n_large > 0) {
         DevBuf<int2> items(n_large, s);
         TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)nlg.get(),
-                  (const int32_t*)lbase.get(), items.get());
-        int64_t blocks = (int64_t)num_cus() * 2;
-        if (blocks > n_large) blocks = n_large;
+                  (const int32_t*)lbase.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
+                  (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
         int32_t dcap = 64;
         while (dcap < dmax_large) dcap <<= 1;
-        // tab: 2*next_pow2(d) <= 4*dcap slots, P: dcap+1, S: dcap
-        const size_t lds_bytes = sizeof(int32_t) * (size_t)(4 * dcap + 2 * dcap + 2);
+        // tab: next_pow2(2d) <= 2*dcap slots, P: kJL+1, S: kJL
+        const size_t per_block = (size_t)(2 * dcap + 2 * kJL + 1);
+        const size_t lds_bytes = sizeof(int32_t) * per_block;
+        int64_t blocks = (int64_t)num_cus() * (lds_bytes <= 20 * 1024 ? 8 : lds_bytes <= 40 * 1024 ? 4 : 2);
+        if (blocks > n_large) blocks = n_large;
         DevBuf<int32_t> gscr;
         size_t dyn = lds_bytes;
         if (lds_bytes > 64 * 1024) {
-            gscr.reset((size_t)blocks * (size_t)(4 * dcap + 2 * dcap + 2), s);
+            gscr.reset((size_t)blocks * per_block, s);
             dyn = 0;
         }
         TC_LAUNCH("light_large", k_light_large, dim3((unsigned)blocks), dim3(256), dyn, s, (const int2*)items.get(),
-                  n_large, (const int32_t*)rpO.get(), (const int32_t*)colO.get(), cfg.chunk_large, dcap, gscr.get(),
-                  acc.get());
+                  n_large, (const int32_t*)rpO.get(), (const int32_t*)colO.get(), (const int32_t*)rpD.get(),
+                  (const int32_t*)colD.get(), (const int32_t*)code.get(), vcap, dcap, gscr.get(), acc.get());
     }
 
     // 5. heavy phase
@@ -584,9 +756,11 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
     res.light_out_edges = hacc[kLightOut];
     res.wedges = hacc[kWedges];
     res.gather = hacc[kGather];
-    res.light_sources_large = hacc[kSrcLarge];
-    res.light_out_edges_large = hacc[kOutLarge];
-    res.gather_large = hacc[kGatherLarge];
+    res.probes = hacc[kProbes];
+    res.items_small = hacc[kItemsSmall];
+    res.items_large = hacc[kItemsLarge];
+    res.model_bytes_small = hacc[kBytesSmall];
+    res.model_bytes_large = hacc[kBytesLarge];
     *out = res;
 }
 

@@ -145,10 +145,9 @@ void compact_kept(const int32_t* col, const int32_t* src, int64_t E2, const uint
 
 struct CountConfig {
     int32_t heavy_num = 1, heavy_den = 1;
-    int32_t small_dmax = 256;        // light sources with d+ <= small_dmax use a wave each
-    int32_t chunk_small = 16384;     // gather positions per small item
-    int32_t chunk_large = 65536;     // gather positions per large item
-    int32_t light_blocks_per_cu = 8; // persistent grid of the small-bin kernel
+    int32_t small_dmax = 256;        // anchors with d+ <= small_dmax use a wave each, others a block
+    int32_t vmajor_cap = 1024;       // pairs with d+(u) <= d+(v) <= cap are closed from v's side (0: never)
+    int32_t light_blocks_per_cu = 8; // persistent grid of the wave-per-item kernel
 };
 
 // Exact count of the graph, or of its copy sampled with (thr, salt) if sampled != 0.
@@ -161,7 +160,10 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
 
 void rp_trace(const tc_graph_s* g, int32_t k, uint64_t seed, hipStream_t s, int64_t* q_host);
 
-// Autotuned parameters for a graph signature (tc_tune.cpp)
+// Autotuned parameters for a graph signature (tc_tune.hip)
 CountConfig tuned_config(const tc_graph_s* g, int sampled, double p, const CountConfig& base);
+void tune_store(const tc_graph_s* g, int sampled, double p, const CountConfig& c);
+bool tune_lookup(const tc_graph_s* g, int sampled, double p, CountConfig* c);
+CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, uint64_t salt, hipStream_t s);
 
 }  // namespace tc

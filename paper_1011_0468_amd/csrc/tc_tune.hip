@@ -1,8 +1,10 @@
-// Launch-parameter table of the autotuner.  Entries are keyed by a graph
-// signature; they change only speed (chunk sizes, persistent grid size) and,
-// for the heavy multiplier, the reported light/heavy split, never the count.
+// Autotuner: a table of launch parameters keyed by graph signature and
+// operating point, filled by timing a fixed candidate grid.  Entries change
+// speed and the reported light/heavy split only; the count is invariant, and
+// the tuner checks that every candidate returns the same T.
 #include "tc_internal.h"
 
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -15,7 +17,7 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int64_t, int64_t, int, int64_t>, CountConfig> g_table;
 
 std::tuple<int64_t, int64_t, int, int64_t> key_of(const tc_graph_s* g, int sampled, double p) {
-    return std::make_tuple(g->n, g->m, sampled, (int64_t)(p * 1e6 + 0.5));
+    return std::make_tuple(g->n, g->m, sampled, sampled ? (int64_t)(p * 1e6 + 0.5) : (int64_t)1000000);
 }
 }  // namespace
 
@@ -28,6 +30,46 @@ CountConfig tuned_config(const tc_graph_s* g, int sampled, double p, const Count
 void tune_store(const tc_graph_s* g, int sampled, double p, const CountConfig& c) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_table[key_of(g, sampled, p)] = c;
+}
+
+bool tune_lookup(const tc_graph_s* g, int sampled, double p, CountConfig* c) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_table.find(key_of(g, sampled, p));
+    if (it == g_table.end()) return false;
+    *c = it->second;
+    return true;
+}
+
+CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, uint64_t salt, hipStream_t s) {
+    const int32_t heavy[3][2] = {{1, 2}, {1, 1}, {2, 1}};
+    const int32_t caps[2] = {0, 1024};
+    const int32_t dmaxs[2] = {128, 256};
+    CountConfig best;
+    double best_ms = 1e300;
+    int64_t T = -1;
+    for (auto& hv : heavy)
+        for (int32_t cap : caps)
+            for (int32_t dm : dmaxs) {
+                CountConfig c;
+                c.heavy_num = hv[0];
+                c.heavy_den = hv[1];
+                c.vmajor_cap = cap;
+                c.small_dmax = dm;
+                tc_counts r;
+                count_core(g, sampled, thr, salt, c, s, &r);  // warm-up (allocations, caches)
+                const auto t0 = std::chrono::steady_clock::now();
+                count_core(g, sampled, thr, salt, c, s, &r);
+                const double ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                if (T >= 0 && r.triangles != T) fail(TC_ERR_DEVICE, "autotune: candidates disagree on the count");
+                T = r.triangles;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+    tune_store(g, sampled, p, best);
+    return best;
 }
 
 }  // namespace tc

@@ -165,3 +165,42 @@ def test_invalid_p_and_groups(gpu):
             gpu.tc_sample(g, p, 0)
     with pytest.raises(gpu.TcError):
         gpu.tc_estimate(g, 0.5, [0, 1, 2], num_groups=2)
+
+
+TUNINGS = [dict(vmajor_cap=0, small_dmax=256), dict(vmajor_cap=1024, small_dmax=256),
+           dict(vmajor_cap=4, small_dmax=32), dict(vmajor_cap=1 << 30, small_dmax=256),
+           dict(vmajor_cap=1 << 30, small_dmax=1), dict(vmajor_cap=0, small_dmax=1)]
+
+
+@pytest.mark.parametrize("name", ["cl16k", "cl_dense", "k65", "multi_loops", "wheel12"])
+def test_counts_invariant_under_launch_tunings(gpu, name):
+    G = GRAPHS[name]
+    g = _build(gpu, G)
+    og = oracle.normalise(*G)
+    want = oracle.count_split(og, 1, 1)
+    for p in (1.0, 0.5):
+        wp = want if p == 1.0 else oracle.count_split(oracle.sample(og, p, 3), 1, 1)
+        for t in TUNINGS:
+            _log("tuning %s p=%g %r" % (name, p, t))
+            gpu.tc_tune_set(g, p, heavy=(1, 1), blocks_per_cu=2, **t)
+            if p == 1.0:
+                got = gpu.tc_count_exact(g, tuned=True)
+            else:
+                got = gpu.tc_estimate(g, p, [3], tuned=True)[0][0]
+            for k in ("triangles", "light", "heavy", "n_heavy", "m"):
+                assert got[k] == wp[k], (name, p, t, k, got[k], wp[k])
+            assert got["probes"] <= got["gather"]
+            if t["vmajor_cap"] == 0:
+                assert got["probes"] == got["gather"]
+
+
+def test_autotune_keeps_the_count(gpu):
+    G = GRAPHS["cl_dense"]
+    g = _build(gpu, G)
+    og = oracle.normalise(*G)
+    best = gpu.tc_autotune(g, 0.5, seed=1)
+    assert best == gpu.tc_tune_get(g, 0.5)
+    got = gpu.tc_estimate(g, 0.5, [1], tuned=True)[0][0]
+    assert got["triangles"] == oracle.count(oracle.sample(og, 0.5, 1))
+    a, b = best["heavy_num"], best["heavy_den"]
+    assert got["heavy"] == oracle.count_split(oracle.sample(og, 0.5, 1), a, b)["heavy"]
