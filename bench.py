@@ -101,6 +101,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="library defaults instead of autotuned launch parameters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -129,14 +130,20 @@ def main():
     del src, dst
     info = g.info()
 
+    tuned = not args.no_tune
+    tunings = {}
+    if tuned:  # untimed: pick launch parameters per operating point; the threshold stays deg <= sqrt(m')
+        for p in ps:
+            tunings[str(p)] = tc.tc_autotune(g, p, seed=args.seed, search_heavy=False)
+
     def step():
         out = []
         for p in ps:
             if p == 1.0:
-                c = tc.tc_count_exact(g)
+                c = tc.tc_count_exact(g, tuned=tuned)
                 c["est"] = float(c["triangles"])
             else:
-                per, ests, _ = tc.tc_estimate(g, p, [args.seed])
+                per, ests, _ = tc.tc_estimate(g, p, [args.seed], tuned=tuned)
                 c = per[0]
                 c["est"] = ests[0]
             c["p"] = p
@@ -151,9 +158,9 @@ def main():
         torch.cuda.synchronize()
         t = time.perf_counter()
         if p == 1.0:
-            tc.tc_count_exact(g)
+            tc.tc_count_exact(g, tuned=tuned)
         else:
-            tc.tc_estimate(g, p, [args.seed])
+            tc.tc_estimate(g, p, [args.seed], tuned=tuned)
         torch.cuda.synchronize()
         per_call_ms.append(round((time.perf_counter() - t) * 1e3, 3))
 
@@ -205,6 +212,7 @@ def main():
         "roofline": roofline,
         "csr_build_ms": round(csr_ms, 2),
         "per_call_ms": dict(zip([str(p) for p in ps], per_call_ms)),
+        "tunings": tunings,
         "results": [{k: c[k] for k in ("p", "m", "triangles", "light", "heavy", "n_heavy", "est")} for c in res],
     }
     if not args.no_cpu_baseline:

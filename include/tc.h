@@ -158,11 +158,12 @@ typedef struct {
 tc_status tc_tune_set(tc_graph g, double p, const tc_tuning* t);
 tc_status tc_tune_get(tc_graph g, double p, tc_tuning* t);
 
-/* Time every candidate of a fixed grid (heavy multiplier in {1/2, 1, 2},
-   vmajor_cap in {0, 1024}, small_dmax in {128, 256}) on the graph sampled
-   with (p, seed), store the fastest and return it in *best (may be NULL).
-   Counts of all candidates must agree; TC_ERR_DEVICE otherwise. */
-tc_status tc_autotune(tc_graph g, double p, uint64_t seed, void* stream, tc_tuning* best);
+/* Time every candidate of a fixed grid (vmajor_cap in {0, 1024},
+   small_dmax in {128, 256}, and, if search_heavy, the heavy multiplier in
+   {1/2, 1, 2}; else the multiplier of the stored entry or 1) on the graph
+   sampled with (p, seed), store the fastest and return it in *best (may be
+   NULL).  Counts of all candidates must agree; TC_ERR_DEVICE otherwise. */
+tc_status tc_autotune(tc_graph g, double p, uint64_t seed, int32_t search_heavy, void* stream, tc_tuning* best);
 
 /* Release a graph (NULL is ignored). */
 void tc_graph_free(tc_graph g);

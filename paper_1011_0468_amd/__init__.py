@@ -153,10 +153,10 @@ def tc_tune_get(g, p):
     return t.as_dict()
 
 
-def tc_autotune(g, p, seed=0, stream=None):
+def tc_autotune(g, p, seed=0, search_heavy=True, stream=None):
     t = TcTuning()
-    check(_native.load().tc_autotune(g.handle, float(p), int(seed) & (2 ** 64 - 1), _stream_ptr(stream),
-                                     ctypes.byref(t)))
+    check(_native.load().tc_autotune(g.handle, float(p), int(seed) & (2 ** 64 - 1), 1 if search_heavy else 0,
+                                     _stream_ptr(stream), ctypes.byref(t)))
     return t.as_dict()
 
 

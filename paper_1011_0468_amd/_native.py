@@ -76,7 +76,7 @@ def load():
         "tc_rp_trace": [vp, i32, u64, vp, P(i64), P(dbl)],
         "tc_tune_set": [vp, dbl, P(TcTuning)],
         "tc_tune_get": [vp, dbl, P(TcTuning)],
-        "tc_autotune": [vp, dbl, u64, vp, P(TcTuning)],
+        "tc_autotune": [vp, dbl, u64, i32, vp, P(TcTuning)],
         "tc_profile_enable": [i32],
         "tc_profile_reset": [],
         "tc_profile_select": [ctypes.c_char_p],

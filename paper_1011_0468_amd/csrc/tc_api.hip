@@ -513,12 +513,13 @@ tc_status tc_tune_get(tc_graph g, double p, tc_tuning* t) {
     });
 }
 
-tc_status tc_autotune(tc_graph g, double p, uint64_t seed, void* stream, tc_tuning* best) {
+tc_status tc_autotune(tc_graph g, double p, uint64_t seed, int32_t search_heavy, void* stream, tc_tuning* best) {
     return guarded([&] {
         if (!g) fail(TC_ERR_INVALID, "graph is NULL");
         if (!p_valid(p)) fail(TC_ERR_INVALID, "p must be finite and in (0, 1]");
         const int sampled = p < 1.0 ? 1 : 0;
-        CountConfig c = autotune(g, sampled, p, keep_threshold(p), sample_salt(seed), (hipStream_t)stream);
+        CountConfig c =
+            autotune(g, sampled, p, keep_threshold(p), sample_salt(seed), search_heavy, (hipStream_t)stream);
         if (best) to_tuning(c, best);
     });
 }

@@ -326,7 +326,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Closure tests for positions [a, b) of the concatenated streamed lists:
 // position g lies in list j (P[j] <= g < P[j+1]) at offset g - P[j] of the
-// list starting at colO[S[j]].  Lists are streamed one after another in
+// list starting at colO[S[j]]; d lists, none empty.  Lists are streamed one after another in
 // super-strips of 64 * U positions: each lane issues U independent loads
 // before probing.  Only the first list is located by search.  Whole wave.
 template <int U>
@@ -376,21 +376,24 @@ __device__ __forceinline__ void build_hash(int32_t rs, int32_t d, const int32_t*
 }
 
 // Stage the iterated entries L[0..cnt) (cnt <= kJL): for entry y, the streamed
-// list is N+(y) (start S, prefix P of lengths) if the pair is closed from this
-// anchor, else an empty list.  kind_u: anchor x = u, entries y = v in N+(u);
-// else anchor x = v, entries y = u in N-(v).  Returns the total length.
+// list is N+(y) if the pair is closed from this anchor, else nothing.  kind_u:
+// anchor x = u, entries y = v in N+(u); else anchor x = v, entries y = u in
+// N-(v).  Non-empty lists are compacted in entry order into S (start in colO)
+// and P (exclusive prefix of lengths, P[nl] = total).  Returns nl; *total
+// receives the number of positions.
 template <int NT>
 __device__ __forceinline__ int32_t stage_lists(const int32_t* __restrict__ L, int32_t cnt, bool kind_u, int32_t dx,
                                                int32_t vcap, const int32_t* __restrict__ rpO,
                                                const int32_t* __restrict__ code, int32_t* P, int32_t* S,
-                                               int32_t* red, int t) {
-    constexpr int R = kJL / NT > 0 ? (kJL + NT - 1) / NT : 1;
+                                               int32_t* red, int t, int32_t* total) {
+    constexpr int R = (kJL + NT - 1) / NT;
     int32_t y[R], st[R], ln[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int j = t * R + k;  // consecutive entries per thread
         y[k] = j < cnt ? L[j] : -1;
     }
+    int32_t loc = 0, nloc = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         st[k] = 0;
@@ -404,28 +407,79 @@ __device__ __forceinline__ int32_t stage_lists(const int32_t* __restrict__ L, in
             else { const int32_t cu = code[y[k]]; take = cu > 0 && vmajor(cu, dx, vcap); }
             ln[k] = take ? dy : 0;
         }
+        loc += ln[k];
+        nloc += ln[k] > 0 ? 1 : 0;
     }
-    int32_t loc = 0;
-#pragma unroll
-    for (int k = 0; k < R; ++k) loc += ln[k];
-    int32_t ex, tot;
+    // two exclusive scans: positions and list slots
+    int32_t ex, tot, nex, ntot;
     if (NT == 64) {
         const int32_t inc = wave_inclusive_sum(loc);
         ex = inc - loc;
         tot = __shfl(inc, 63, 64);
+        const int32_t ninc = wave_inclusive_sum(nloc);
+        nex = ninc - nloc;
+        ntot = __shfl(ninc, 63, 64);
     } else {
         ex = block_exclusive_sum<NT>(loc, red, &tot);
+        nex = block_exclusive_sum<NT>(nloc, red, &ntot);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        const int j = t * R + k;
-        if (j < cnt) {
-            S[j] = st[k];
+        if (ln[k] > 0) {
+            S[nex] = st[k];
+            P[nex] = ex;
             ex += ln[k];
-            P[j + 1] = ex;
+            ++nex;
         }
     }
-    return tot;
+    if (t == 0) P[ntot] = tot;
+    *total = tot;
+    return ntot;
+}
+
+// Packed variant of close_range for short lists: each 64-position strip may
+// span several lists.  The owner list of every lane is found with an LDS mark
+// (the strip offset where each following list starts) and a wave max-scan.
+// `mark` is 64 ints of per-wave LDS.  P is strictly increasing (no empty lists).
+template <int U>
+__device__ __forceinline__ int32_t close_range_packed(const int32_t* P, const int32_t* S, int nl, int32_t a,
+                                                      int32_t b, const int32_t* __restrict__ colO, const int32_t* tab,
+                                                      int lg, int32_t* mark, int lane) {
+    int32_t cnt = 0;
+    if (a >= b) return 0;
+    int jcur = find_list(P, nl, a);
+    for (int32_t g0 = a; g0 < b; g0 += 64 * U) {
+        int32_t x[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int32_t gs = g0 + 64 * k;  // strip start
+            x[k] = -1;
+            if (gs < b) {  // wave-uniform
+                mark[lane] = -1;
+                wave_lds_sync();
+                const int j = jcur + 1 + lane;
+                if (j < nl) {
+                    const int32_t off = P[j] - gs;
+                    if (off < 64) mark[off] = j;
+                }
+                wave_lds_sync();
+                int32_t o = mark[lane];
+                o = o > jcur ? o : jcur;
+#pragma unroll
+                for (int dd = 1; dd < 64; dd <<= 1) {
+                    const int32_t q = __shfl_up(o, dd, 64);
+                    if (lane >= dd) o = q > o ? q : o;
+                }
+                jcur = __shfl(o, 63, 64);
+                const int32_t g = gs + lane;
+                if (g < b) x[k] = colO[S[o] + (g - P[o])];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (x[k] >= 0) cnt += hash_contains(tab, lg, x[k]);
+    }
+    return cnt;
 }
 
 // One wave per item, persistent over items with a static stride.  Item
@@ -438,12 +492,13 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
                                                       const int32_t* __restrict__ code, int32_t vcap,
                                                       int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 2 * DS;
-    __shared__ int32_t lds[4][HS_MAX + 2 * kJL + 1];
+    __shared__ int32_t lds[4][HS_MAX + 2 * kJL + 1 + 64];
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
     int32_t* tab = lds[w];
     int32_t* P = tab + HS_MAX;
     int32_t* S = P + kJL + 1;
+    int32_t* mark = S + kJL;
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
     int64_t total = 0;
@@ -466,9 +521,11 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         if (lane == 0) P[0] = 0;
         wave_lds_sync();
         build_hash<64>(rs, d, colO, tab, lg, lane);
-        const int32_t W = stage_lists<64>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, nullptr, lane);
+        int32_t W;
+        const int32_t nl = stage_lists<64>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, nullptr, lane, &W);
         wave_lds_sync();
-        total += close_range<4>(P, S, cnt, 0, W, colO, tab, lg, lane);
+        if (kind_u) total += close_range<4>(P, S, nl, 0, W, colO, tab, lg, lane);
+        else total += close_range_packed<4>(P, S, nl, 0, W, colO, tab, lg, mark, lane);
         wave_lds_sync();
     }
     total = wave_sum(total);
@@ -486,8 +543,8 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
                                                       int32_t* __restrict__ gscratch, int64_t* __restrict__ acc) {
     extern __shared__ int32_t dyn[];
     __shared__ int32_t red[5];
-    // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL)
-    const int64_t per_block = 2 * (int64_t)dcap + 2 * kJL + 1;
+    // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL), marks (4 x 64)
+    const int64_t per_block = 2 * (int64_t)dcap + 2 * kJL + 1 + 256;
     int32_t* base = gscratch ? gscratch + (int64_t)blockIdx.x * per_block : dyn;
     int32_t* tab = base;
     int32_t* P = base + 2 * dcap;
@@ -515,12 +572,14 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         if (t == 0) P[0] = 0;
         __syncthreads();
         build_hash<256>(rs, d, colO, tab, lg, t);
-        const int32_t W = stage_lists<256>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, red, t);
+        int32_t W;
+        const int32_t nl = stage_lists<256>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, red, t, &W);
         __syncthreads();
         const int32_t q = (W + 3) / 4;
         const int32_t a = min(w * q, W);
         const int32_t b = min(a + q, W);
-        total += close_range<4>(P, S, cnt, a, b, colO, tab, lg, lane);
+        if (kind_u) total += close_range<4>(P, S, nl, a, b, colO, tab, lg, lane);
+        else total += close_range_packed<4>(P, S, nl, a, b, colO, tab, lg, S + kJL + 64 * w, lane);
         __syncthreads();
     }
     total = wave_sum(total);
@@ -708,8 +767,8 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
                   (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
         int32_t dcap = 64;
         while (dcap < dmax_large) dcap <<= 1;
-        // tab: next_pow2(2d) <= 2*dcap slots, P: kJL+1, S: kJL
-        const size_t per_block = (size_t)(2 * dcap + 2 * kJL + 1);
+        // tab: next_pow2(2d) <= 2*dcap slots, P: kJL+1, S: kJL, marks: 4*64
+        const size_t per_block = (size_t)(2 * dcap + 2 * kJL + 1 + 256);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
         int64_t blocks = (int64_t)num_cus() * (lds_bytes <= 20 * 1024 ? 8 : lds_bytes <= 40 * 1024 ? 4 : 2);
         if (blocks > n_large) blocks = n_large;

@@ -164,6 +164,7 @@ void rp_trace(const tc_graph_s* g, int32_t k, uint64_t seed, hipStream_t s, int6
 CountConfig tuned_config(const tc_graph_s* g, int sampled, double p, const CountConfig& base);
 void tune_store(const tc_graph_s* g, int sampled, double p, const CountConfig& c);
 bool tune_lookup(const tc_graph_s* g, int sampled, double p, CountConfig* c);
-CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, uint64_t salt, hipStream_t s);
+CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, uint64_t salt, int search_heavy,
+                     hipStream_t s);
 
 }  // namespace tc

@@ -40,19 +40,29 @@ bool tune_lookup(const tc_graph_s* g, int sampled, double p, CountConfig* c) {
     return true;
 }
 
-CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, uint64_t salt, hipStream_t s) {
-    const int32_t heavy[3][2] = {{1, 2}, {1, 1}, {2, 1}};
+CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, uint64_t salt, int search_heavy,
+                     hipStream_t s) {
+    CountConfig cur;
+    tune_lookup(g, sampled, p, &cur);
+    int32_t heavy[3][2] = {{1, 2}, {1, 1}, {2, 1}};
+    int nh = 3;
+    if (!search_heavy) {
+        heavy[0][0] = cur.heavy_num;
+        heavy[0][1] = cur.heavy_den;
+        nh = 1;
+    }
     const int32_t caps[2] = {0, 1024};
     const int32_t dmaxs[2] = {128, 256};
     CountConfig best;
     double best_ms = 1e300;
     int64_t T = -1;
-    for (auto& hv : heavy)
+    for (int hi = 0; hi < nh; ++hi)
         for (int32_t cap : caps)
             for (int32_t dm : dmaxs) {
                 CountConfig c;
-                c.heavy_num = hv[0];
-                c.heavy_den = hv[1];
+                c.heavy_num = heavy[hi][0];
+                c.heavy_den = heavy[hi][1];
+                c.light_blocks_per_cu = cur.light_blocks_per_cu;
                 c.vmajor_cap = cap;
                 c.small_dmax = dm;
                 tc_counts r;

@@ -198,7 +198,7 @@ def test_autotune_keeps_the_count(gpu):
     G = GRAPHS["cl_dense"]
     g = _build(gpu, G)
     og = oracle.normalise(*G)
-    best = gpu.tc_autotune(g, 0.5, seed=1)
+    best = gpu.tc_autotune(g, 0.5, seed=1, search_heavy=True)
     assert best == gpu.tc_tune_get(g, 0.5)
     got = gpu.tc_estimate(g, 0.5, [1], tuned=True)[0][0]
     assert got["triangles"] == oracle.count(oracle.sample(og, 0.5, 1))
