@@ -53,6 +53,8 @@ int num_cus() {
 
 // Entries of an iterated list processed by one work item.
 constexpr int kJL = 256;
+// Strips of 64 positions per super-strip of the closure loop.
+constexpr int kU = 4;
 
 // ---------------------------------------------------------------------------
 // orientation
@@ -324,35 +326,89 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Membership tests of up to U keys (x[k] < 0: no key) against the hash set,
+// with the U probe sequences advanced together so that every step issues U
+// independent LDS reads.  Returns the number of keys found.
+template <int U>
+__device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const int32_t (&x)[U]) {
+    const uint32_t mask = (1u << lg) - 1;
+    uint32_t sl[U];
+    uint32_t live = 0;
+    int32_t found = 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        sl[k] = x[k] >= 0 ? hslot(x[k], lg) : 0u;
+        live |= (x[k] >= 0 ? 1u : 0u) << k;
+    }
+    while (live) {
+        int32_t key[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) key[k] = ((live >> k) & 1u) ? tab[sl[k]] : -1;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (!((live >> k) & 1u)) continue;
+            if (key[k] == x[k]) { ++found; live &= ~(1u << k); }
+            else if (key[k] == -1) live &= ~(1u << k);
+            else sl[k] = (sl[k] + 1) & mask;
+        }
+    }
+    return found;
+}
+
 // Closure tests for positions [a, b) of the concatenated streamed lists:
 // position g lies in list j (P[j] <= g < P[j+1]) at offset g - P[j] of the
-// list starting at colO[S[j]]; d lists, none empty.  Lists are streamed one after another in
-// super-strips of 64 * U positions: each lane issues U independent loads
-// before probing.  Only the first list is located by search.  Whole wave.
+// list starting at colO[S[j]]; nl lists, none empty, so P is strictly
+// increasing.  Positions go in super-strips of 64 * U: the lists that start
+// inside a super-strip (at most 64 * U of them, the ones after the owner of its
+// first position) are marked at their start offsets in `mark` (64 * U ints of
+// per-wave LDS), and each lane's owner is the running maximum of the marks,
+// one 64-lane max-scan per strip.  All U gathers are issued before the probes.
+// Called by a whole wave.
 template <int U>
-__device__ __forceinline__ int32_t close_range(const int32_t* P, const int32_t* S, int d, int32_t a, int32_t b,
-                                               const int32_t* __restrict__ colO, const int32_t* tab, int lg,
-                                               int lane) {
+__device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* S, int nl, int32_t a, int32_t b,
+                                              const int32_t* __restrict__ colO, const int32_t* tab, int lg,
+                                              int32_t* mark, int lane) {
     int32_t cnt = 0;
     if (a >= b) return 0;
-    int j = find_list(P, d, a);
-    int32_t pos = a;
-    while (pos < b) {
-        const int32_t lend = min(P[j + 1], b);
-        const int32_t base = S[j] - P[j];
-        for (int32_t g0 = pos; g0 < lend; g0 += 64 * U) {
-            int32_t x[U];
+    int jlo = find_list(P, nl, a);
+    for (int32_t g0 = a; g0 < b; g0 += 64 * U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) mark[lane + 64 * k] = -1;
+        wave_lds_sync();
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int j = jlo + 1 + lane + 64 * k;
+            if (j < nl) {
+                const int32_t off = P[j] - g0;  // >= 0: list jlo + 1 starts after position g0 - 1
+                if (off < 64 * U) mark[off] = j;
+            }
+        }
+        wave_lds_sync();
+        int32_t o[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) o[k] = mark[lane + 64 * k];
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
 #pragma unroll
             for (int k = 0; k < U; ++k) {
-                const int32_t g = g0 + lane + 64 * k;
-                x[k] = g < lend ? colO[base + g] : -1;
+                const int32_t q = __shfl_up(o[k], dd, 64);
+                if (lane >= dd) o[k] = q > o[k] ? q : o[k];
             }
-#pragma unroll
-            for (int k = 0; k < U; ++k)
-                if (x[k] >= 0) cnt += hash_contains(tab, lg, x[k]);
         }
-        pos = lend;
-        ++j;
+        int32_t carry = jlo;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            o[k] = o[k] > carry ? o[k] : carry;
+            carry = __shfl(o[k], 63, 64);
+        }
+        jlo = carry;
+        int32_t x[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int32_t g = g0 + lane + 64 * k;
+            x[k] = g < b ? colO[S[o[k]] + (g - P[o[k]])] : -1;
+        }
+        cnt += probe_many<U>(tab, lg, x);
     }
     return cnt;
 }
@@ -437,51 +493,6 @@ __device__ __forceinline__ int32_t stage_lists(const int32_t* __restrict__ L, in
     return ntot;
 }
 
-// Packed variant of close_range for short lists: each 64-position strip may
-// span several lists.  The owner list of every lane is found with an LDS mark
-// (the strip offset where each following list starts) and a wave max-scan.
-// `mark` is 64 ints of per-wave LDS.  P is strictly increasing (no empty lists).
-template <int U>
-__device__ __forceinline__ int32_t close_range_packed(const int32_t* P, const int32_t* S, int nl, int32_t a,
-                                                      int32_t b, const int32_t* __restrict__ colO, const int32_t* tab,
-                                                      int lg, int32_t* mark, int lane) {
-    int32_t cnt = 0;
-    if (a >= b) return 0;
-    int jcur = find_list(P, nl, a);
-    for (int32_t g0 = a; g0 < b; g0 += 64 * U) {
-        int32_t x[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int32_t gs = g0 + 64 * k;  // strip start
-            x[k] = -1;
-            if (gs < b) {  // wave-uniform
-                mark[lane] = -1;
-                wave_lds_sync();
-                const int j = jcur + 1 + lane;
-                if (j < nl) {
-                    const int32_t off = P[j] - gs;
-                    if (off < 64) mark[off] = j;
-                }
-                wave_lds_sync();
-                int32_t o = mark[lane];
-                o = o > jcur ? o : jcur;
-#pragma unroll
-                for (int dd = 1; dd < 64; dd <<= 1) {
-                    const int32_t q = __shfl_up(o, dd, 64);
-                    if (lane >= dd) o = q > o ? q : o;
-                }
-                jcur = __shfl(o, 63, 64);
-                const int32_t g = gs + lane;
-                if (g < b) x[k] = colO[S[o] + (g - P[o])];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < U; ++k)
-            if (x[k] >= 0) cnt += hash_contains(tab, lg, x[k]);
-    }
-    return cnt;
-}
-
 // One wave per item, persistent over items with a static stride.  Item
 // (x, r): anchor x, kind u (x >= 0) or v (encoded ~x), entries r*kJL.. of the
 // iterated list.  LDS per wave: hash (2*DS slots), P (kJL+1), S (kJL).
@@ -492,7 +503,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
                                                       const int32_t* __restrict__ code, int32_t vcap,
                                                       int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 2 * DS;
-    __shared__ int32_t lds[4][HS_MAX + 2 * kJL + 1 + 64];
+    __shared__ int32_t lds[4][HS_MAX + 2 * kJL + 1 + 64 * kU];
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
     int32_t* tab = lds[w];
@@ -524,8 +535,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         int32_t W;
         const int32_t nl = stage_lists<64>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, nullptr, lane, &W);
         wave_lds_sync();
-        if (kind_u) total += close_range<4>(P, S, nl, 0, W, colO, tab, lg, lane);
-        else total += close_range_packed<4>(P, S, nl, 0, W, colO, tab, lg, mark, lane);
+        total += close_flat<kU>(P, S, nl, 0, W, colO, tab, lg, mark, lane);
         wave_lds_sync();
     }
     total = wave_sum(total);
@@ -543,8 +553,8 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
                                                       int32_t* __restrict__ gscratch, int64_t* __restrict__ acc) {
     extern __shared__ int32_t dyn[];
     __shared__ int32_t red[5];
-    // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL), marks (4 x 64)
-    const int64_t per_block = 2 * (int64_t)dcap + 2 * kJL + 1 + 256;
+    // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL), marks (4 x 64 kU)
+    const int64_t per_block = 2 * (int64_t)dcap + 2 * kJL + 1 + 256 * kU;
     int32_t* base = gscratch ? gscratch + (int64_t)blockIdx.x * per_block : dyn;
     int32_t* tab = base;
     int32_t* P = base + 2 * dcap;
@@ -578,8 +588,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         const int32_t q = (W + 3) / 4;
         const int32_t a = min(w * q, W);
         const int32_t b = min(a + q, W);
-        if (kind_u) total += close_range<4>(P, S, nl, a, b, colO, tab, lg, lane);
-        else total += close_range_packed<4>(P, S, nl, a, b, colO, tab, lg, S + kJL + 64 * w, lane);
+        total += close_flat<kU>(P, S, nl, a, b, colO, tab, lg, S + kJL + 64 * kU * w, lane);
         __syncthreads();
     }
     total = wave_sum(total);
@@ -767,8 +776,8 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
                   (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
         int32_t dcap = 64;
         while (dcap < dmax_large) dcap <<= 1;
-        // tab: next_pow2(2d) <= 2*dcap slots, P: kJL+1, S: kJL, marks: 4*64
-        const size_t per_block = (size_t)(2 * dcap + 2 * kJL + 1 + 256);
+        // tab: next_pow2(2d) <= 2*dcap slots, P: kJL+1, S: kJL, marks: 4*64*kU
+        const size_t per_block = (size_t)(2 * dcap + 2 * kJL + 1 + 256 * kU);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
         int64_t blocks = (int64_t)num_cus() * (lds_bytes <= 20 * 1024 ? 8 : lds_bytes <= 40 * 1024 ? 4 : 2);
         if (blocks > n_large) blocks = n_large;
