@@ -320,8 +320,13 @@ __device__ __forceinline__ int find_list(const int32_t* P, int d, int32_t g) {
     return lo;
 }
 
+// Orders one wave's shared-table writes before its later reads: a full
+// s_waitcnt (the wavefront-scope fences alone emit no wait, and the tables may
+// be reached through flat or global instructions, which complete
+// asynchronously), then a scheduling barrier.
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
@@ -543,9 +548,11 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
 }
 
 // One block (4 waves) per item for anchors with large out-lists.  The hash
-// set and the list tables live in dynamic LDS, or in a global scratch slice per
-// block when they do not fit.  After staging, each wave closes a quarter of
-// the item's positions.
+// set and the list tables live in dynamic LDS (GLOBAL = false: the compiler
+// sees the LDS address space and emits ds_* instructions), or in a global
+// scratch slice per block when they do not fit (GLOBAL = true).  After
+// staging, each wave closes a quarter of the item's positions.
+template <bool GLOBAL>
 __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ items, int64_t n_items,
                                                       const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
                                                       const int32_t* __restrict__ rpD, const int32_t* __restrict__ colD,
@@ -555,7 +562,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
     __shared__ int32_t red[5];
     // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL), marks (4 x 64 kU)
     const int64_t per_block = 2 * (int64_t)dcap + 2 * kJL + 1 + 256 * kU;
-    int32_t* base = gscratch ? gscratch + (int64_t)blockIdx.x * per_block : dyn;
+    int32_t* base = GLOBAL ? gscratch + (int64_t)blockIdx.x * per_block : dyn;
     int32_t* tab = base;
     int32_t* P = base + 2 * dcap;
     int32_t* S = P + kJL + 1;
@@ -787,9 +794,16 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
             gscr.reset((size_t)blocks * per_block, s);
             dyn = 0;
         }
-        TC_LAUNCH("light_large", k_light_large, dim3((unsigned)blocks), dim3(256), dyn, s, (const int2*)items.get(),
-                  n_large, (const int32_t*)rpO.get(), (const int32_t*)colO.get(), (const int32_t*)rpD.get(),
-                  (const int32_t*)colD.get(), (const int32_t*)code.get(), vcap, dcap, gscr.get(), acc.get());
+        if (dyn > 0)
+            TC_LAUNCH("light_large", k_light_large<false>, dim3((unsigned)blocks), dim3(256), dyn, s,
+                      (const int2*)items.get(), n_large, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
+                      (const int32_t*)rpD.get(), (const int32_t*)colD.get(), (const int32_t*)code.get(), vcap, dcap,
+                      (int32_t*)nullptr, acc.get());
+        else
+            TC_LAUNCH("light_large", k_light_large<true>, dim3((unsigned)blocks), dim3(256), 0, s,
+                      (const int2*)items.get(), n_large, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
+                      (const int32_t*)rpD.get(), (const int32_t*)colD.get(), (const int32_t*)code.get(), vcap, dcap,
+                      gscr.get(), acc.get());
     }
 
     // 5. heavy phase
