@@ -283,10 +283,12 @@ __global__ void k_info(const int32_t* mp, const int32_t* sb, const int32_t* lb, 
 // ---------------------------------------------------------------------------
 
 // multiplicative hash on the 24-bit multiplier (full-rate v_mul_u32_u24), with
-// the high id bits folded in first
+// the high id bits folded in first.  HIP's __umul24 returns a signed int: the
+// product is taken as unsigned before the shift, so the slot is its top lg bits.
 __device__ __forceinline__ uint32_t hslot(int32_t w, int lg) {
     const uint32_t x = (uint32_t)w ^ ((uint32_t)w >> 21);
-    return __umul24(x, 0x9E3779u) >> (32 - lg);
+    const uint32_t prod = (uint32_t)__umul24(x, 0x9E3779u);
+    return prod >> (32 - lg);
 }
 
 __device__ __forceinline__ void hash_insert(int32_t* tab, int lg, int32_t v) {
@@ -342,7 +344,7 @@ __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const 
     int32_t found = 0;
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-        sl[k] = x[k] >= 0 ? hslot(x[k], lg) : 0u;
+        sl[k] = x[k] >= 0 ? (hslot(x[k], lg) & mask) : 0u;
         live |= (x[k] >= 0 ? 1u : 0u) << k;
     }
     while (live) {
