@@ -322,16 +322,21 @@ __device__ __forceinline__ int find_list(const int32_t* P, int d, int32_t g) {
     return lo;
 }
 
-// Orders one wave's shared-table writes before its later reads: a full
-// s_waitcnt (the wavefront-scope fences alone emit no wait, and the tables may
-// be reached through flat or global instructions, which complete
-// asynchronously), then a scheduling barrier.
-__device__ __forceinline__ void wave_lds_sync() {
+// Orders one wave's shared-table writes before its later reads.  LDS
+// operations of a wave complete in order, so for tables in LDS only the
+// compiler must be kept from moving accesses across (fences) and outstanding
+// LDS results are drained (lgkmcnt); global loads stay in flight.  Tables in
+// global scratch (GLOBAL) need every outstanding access drained.
+template <bool GLOBAL>
+__device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_s_waitcnt(0);
+    if (GLOBAL) __builtin_amdgcn_s_waitcnt(0);
+    else __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt unrestricted
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+__device__ __forceinline__ void wave_lds_sync() { wave_sync<false>(); }
 
 // Membership tests of up to U keys (x[k] < 0: no key) against the hash set,
 // with the U probe sequences advanced together so that every step issues U
@@ -362,26 +367,29 @@ __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const 
     return found;
 }
 
-// Closure tests for positions [a, b) of the concatenated streamed lists:
-// position g lies in list j (P[j] <= g < P[j+1]) at offset g - P[j] of the
-// list starting at colO[S[j]]; nl lists, none empty, so P is strictly
-// increasing.  Positions go in super-strips of 64 * U: the lists that start
-// inside a super-strip (at most 64 * U of them, the ones after the owner of its
-// first position) are marked at their start offsets in `mark` (64 * U ints of
-// per-wave LDS), and each lane's owner is the running maximum of the marks,
-// one 64-lane max-scan per strip.  All U gathers are issued before the probes.
-// Called by a whole wave.
-template <int U>
-__device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* S, int nl, int32_t a, int32_t b,
-                                              const int32_t* __restrict__ colO, const int32_t* tab, int lg,
-                                              int32_t* mark, int lane) {
-    int32_t cnt = 0;
-    if (a >= b) return 0;
-    int jlo = find_list(P, nl, a);
-    for (int32_t g0 = a; g0 < b; g0 += 64 * U) {
+// Owners and gathers of one super-strip of 64 * U positions starting at g0
+// (< b): position g lies in list j (P[j] <= g < P[j+1]) at offset g - P[j] of
+// the list starting at colO[S[j]]; nl lists, none empty, so P is strictly
+// increasing.  jlo is the owner of g0 on entry (of g0 + 64U - 1 on exit).
+// When the whole super-strip lies in list jlo every lane owns jlo; otherwise
+// the lists starting inside it (at most 64U, those after jlo) are marked at
+// their start offsets in `mark` (64U ints of per-wave LDS) and each lane's
+// owner is the running maximum of the marks: one 64-lane max-scan per strip.
+// Loads are issued for every lane (clamped to the owner's first entry past b)
+// so the caller can keep them in flight.  Whole wave.
+template <int U, bool GLOBAL>
+__device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* S, int nl, int32_t g0, int32_t b,
+                                              const int32_t* __restrict__ colO, int32_t* mark, int lane, int& jlo,
+                                              int32_t (&x)[U]) {
+    int32_t o[U];
+    const int32_t nxt = jlo + 1 < nl ? P[jlo + 1] : INT32_MAX;
+    if (nxt >= g0 + 64 * U) {  // wave-uniform: one list covers the super-strip
+#pragma unroll
+        for (int k = 0; k < U; ++k) o[k] = jlo;
+    } else {
 #pragma unroll
         for (int k = 0; k < U; ++k) mark[lane + 64 * k] = -1;
-        wave_lds_sync();
+        wave_sync<GLOBAL>();
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int j = jlo + 1 + lane + 64 * k;
@@ -390,8 +398,7 @@ __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* S
                 if (off < 64 * U) mark[off] = j;
             }
         }
-        wave_lds_sync();
-        int32_t o[U];
+        wave_sync<GLOBAL>();
 #pragma unroll
         for (int k = 0; k < U; ++k) o[k] = mark[lane + 64 * k];
 #pragma unroll
@@ -409,13 +416,37 @@ __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* S
             carry = __shfl(o[k], 63, 64);
         }
         jlo = carry;
-        int32_t x[U];
+        wave_sync<GLOBAL>();  // mark reads done before the next super-strip resets it
+    }
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int32_t g = g0 + lane + 64 * k;
-            x[k] = g < b ? colO[S[o[k]] + (g - P[o[k]])] : -1;
-        }
-        cnt += probe_many<U>(tab, lg, x);
+    for (int k = 0; k < U; ++k) {
+        const int32_t g = g0 + lane + 64 * k;
+        const int32_t off = g < b ? g - P[o[k]] : 0;
+        const int32_t v = colO[S[o[k]] + off];
+        x[k] = g < b ? v : -1;
+    }
+}
+
+// Closure tests for positions [a, b) of the concatenated streamed lists
+// (layout as in gather_strips).  Software-pipelined: the gathers of the next
+// super-strip are issued before the hash probes of the current one.
+template <int U, bool GLOBAL>
+__device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* S, int nl, int32_t a, int32_t b,
+                                              const int32_t* __restrict__ colO, const int32_t* tab, int lg,
+                                              int32_t* mark, int lane) {
+    int32_t cnt = 0;
+    if (a >= b) return 0;
+    int jlo = find_list(P, nl, a);
+    int32_t xc[U], xn[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) xn[k] = -1;
+    gather_strips<U, GLOBAL>(P, S, nl, a, b, colO, mark, lane, jlo, xc);
+    for (int32_t g0 = a; g0 < b; g0 += 64 * U) {
+        const int32_t gn = g0 + 64 * U;
+        if (gn < b) gather_strips<U, GLOBAL>(P, S, nl, gn, b, colO, mark, lane, jlo, xn);
+        cnt += probe_many<U>(tab, lg, xc);
+#pragma unroll
+        for (int k = 0; k < U; ++k) xc[k] = xn[k];
     }
     return cnt;
 }
@@ -542,7 +573,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         int32_t W;
         const int32_t nl = stage_lists<64>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, nullptr, lane, &W);
         wave_lds_sync();
-        total += close_flat<kU>(P, S, nl, 0, W, colO, tab, lg, mark, lane);
+        total += close_flat<kU, false>(P, S, nl, 0, W, colO, tab, lg, mark, lane);
         wave_lds_sync();
     }
     total = wave_sum(total);
@@ -597,7 +628,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         const int32_t q = (W + 3) / 4;
         const int32_t a = min(w * q, W);
         const int32_t b = min(a + q, W);
-        total += close_flat<kU>(P, S, nl, a, b, colO, tab, lg, S + kJL + 64 * kU * w, lane);
+        total += close_flat<kU, GLOBAL>(P, S, nl, a, b, colO, tab, lg, S + kJL + 64 * kU * w, lane);
         __syncthreads();
     }
     total = wave_sum(total);
