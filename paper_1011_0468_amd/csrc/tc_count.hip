@@ -53,7 +53,8 @@ int num_cus() {
 
 // Entries of an iterated list processed by one work item.
 constexpr int kJL = 256;
-// Strips of 64 positions per super-strip of the closure loop.
+// Lanes per streamed list, and loads in flight per lane, in the closure loop.
+constexpr int kQ = 16;
 constexpr int kU = 4;
 
 // ---------------------------------------------------------------------------
@@ -367,86 +368,32 @@ __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const 
     return found;
 }
 
-// Owners and gathers of one super-strip of 64 * U positions starting at g0
-// (< b): position g lies in list j (P[j] <= g < P[j+1]) at offset g - P[j] of
-// the list starting at colO[S[j]]; nl lists, none empty, so P is strictly
-// increasing.  jlo is the owner of g0 on entry (of g0 + 64U - 1 on exit).
-// When the whole super-strip lies in list jlo every lane owns jlo; otherwise
-// the lists starting inside it (at most 64U, those after jlo) are marked at
-// their start offsets in `mark` (64U ints of per-wave LDS) and each lane's
-// owner is the running maximum of the marks: one 64-lane max-scan per strip.
-// Loads are issued for every lane (clamped to the owner's first entry past b)
-// so the caller can keep them in flight.  Whole wave.
-template <int U, bool GLOBAL>
-__device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* S, int nl, int32_t g0, int32_t b,
-                                              const int32_t* __restrict__ colO, int32_t* mark, int lane, int& jlo,
-                                              int32_t (&x)[U]) {
-    int32_t o[U];
-    const int32_t nxt = jlo + 1 < nl ? P[jlo + 1] : INT32_MAX;
-    if (nxt >= g0 + 64 * U) {  // wave-uniform: one list covers the super-strip
-#pragma unroll
-        for (int k = 0; k < U; ++k) o[k] = jlo;
-    } else {
-#pragma unroll
-        for (int k = 0; k < U; ++k) mark[lane + 64 * k] = -1;
-        wave_sync<GLOBAL>();
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int j = jlo + 1 + lane + 64 * k;
-            if (j < nl) {
-                const int32_t off = P[j] - g0;  // >= 0: list jlo + 1 starts after position g0 - 1
-                if (off < 64 * U) mark[off] = j;
-            }
-        }
-        wave_sync<GLOBAL>();
-#pragma unroll
-        for (int k = 0; k < U; ++k) o[k] = mark[lane + 64 * k];
-#pragma unroll
-        for (int dd = 1; dd < 64; dd <<= 1) {
+// Closure tests for the staged lists j = j0, j0 + jstride, ... (< nl): list j
+// is N+ of one neighbour, starting at colO[S[j]] with P[j+1] - P[j] entries.
+// Each Q-lane sub-group of the wave streams one list at a time (sub-group s of
+// the wave takes every (64/Q)-th of the lists given), Q * U entries per step
+// with U loads per lane issued before the probes.  No cross-lane
+// communication: lanes only share the read-only tables.
+template <int Q, int U>
+__device__ __forceinline__ int32_t close_lists(const int32_t* P, const int32_t* S, int nl, int j0, int jstride,
+                                               const int32_t* __restrict__ colO, const int32_t* tab, int lg,
+                                               int lane) {
+    constexpr int G = 64 / Q;
+    const int sub = lane / Q;
+    const int q = lane % Q;
+    int32_t cnt = 0;
+    for (int j = j0 + sub * jstride; j < nl; j += G * jstride) {
+        const int32_t len = P[j + 1] - P[j];
+        const int32_t base = S[j];
+        for (int32_t off = q; off < len; off += Q * U) {
+            int32_t x[U];
 #pragma unroll
             for (int k = 0; k < U; ++k) {
-                const int32_t q = __shfl_up(o[k], dd, 64);
-                if (lane >= dd) o[k] = q > o[k] ? q : o[k];
+                const int32_t o = off + Q * k;
+                x[k] = o < len ? colO[base + o] : -1;
             }
+            cnt += probe_many<U>(tab, lg, x);
         }
-        int32_t carry = jlo;
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            o[k] = o[k] > carry ? o[k] : carry;
-            carry = __shfl(o[k], 63, 64);
-        }
-        jlo = carry;
-        wave_sync<GLOBAL>();  // mark reads done before the next super-strip resets it
-    }
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-        const int32_t g = g0 + lane + 64 * k;
-        const int32_t off = g < b ? g - P[o[k]] : 0;
-        const int32_t v = colO[S[o[k]] + off];
-        x[k] = g < b ? v : -1;
-    }
-}
-
-// Closure tests for positions [a, b) of the concatenated streamed lists
-// (layout as in gather_strips).  Software-pipelined: the gathers of the next
-// super-strip are issued before the hash probes of the current one.
-template <int U, bool GLOBAL>
-__device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* S, int nl, int32_t a, int32_t b,
-                                              const int32_t* __restrict__ colO, const int32_t* tab, int lg,
-                                              int32_t* mark, int lane) {
-    int32_t cnt = 0;
-    if (a >= b) return 0;
-    int jlo = find_list(P, nl, a);
-    int32_t xc[U], xn[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) xn[k] = -1;
-    gather_strips<U, GLOBAL>(P, S, nl, a, b, colO, mark, lane, jlo, xc);
-    for (int32_t g0 = a; g0 < b; g0 += 64 * U) {
-        const int32_t gn = g0 + 64 * U;
-        if (gn < b) gather_strips<U, GLOBAL>(P, S, nl, gn, b, colO, mark, lane, jlo, xn);
-        cnt += probe_many<U>(tab, lg, xc);
-#pragma unroll
-        for (int k = 0; k < U; ++k) xc[k] = xn[k];
     }
     return cnt;
 }
@@ -541,13 +488,12 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
                                                       const int32_t* __restrict__ code, int32_t vcap,
                                                       int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 2 * DS;
-    __shared__ int32_t lds[4][HS_MAX + 2 * kJL + 1 + 64 * kU];
+    __shared__ int32_t lds[4][HS_MAX + 2 * kJL + 1];
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
     int32_t* tab = lds[w];
     int32_t* P = tab + HS_MAX;
     int32_t* S = P + kJL + 1;
-    int32_t* mark = S + kJL;
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
     int64_t total = 0;
@@ -573,7 +519,8 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         int32_t W;
         const int32_t nl = stage_lists<64>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, nullptr, lane, &W);
         wave_lds_sync();
-        total += close_flat<kU, false>(P, S, nl, 0, W, colO, tab, lg, mark, lane);
+        (void)W;
+        total += close_lists<kQ, kU>(P, S, nl, 0, 1, colO, tab, lg, lane);
         wave_lds_sync();
     }
     total = wave_sum(total);
@@ -593,8 +540,8 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
                                                       int32_t* __restrict__ gscratch, int64_t* __restrict__ acc) {
     extern __shared__ int32_t dyn[];
     __shared__ int32_t red[5];
-    // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL), marks (4 x 64 kU)
-    const int64_t per_block = 2 * (int64_t)dcap + 2 * kJL + 1 + 256 * kU;
+    // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL)
+    const int64_t per_block = 2 * (int64_t)dcap + 2 * kJL + 1;
     int32_t* base = GLOBAL ? gscratch + (int64_t)blockIdx.x * per_block : dyn;
     int32_t* tab = base;
     int32_t* P = base + 2 * dcap;
@@ -625,10 +572,8 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         int32_t W;
         const int32_t nl = stage_lists<256>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, red, t, &W);
         __syncthreads();
-        const int32_t q = (W + 3) / 4;
-        const int32_t a = min(w * q, W);
-        const int32_t b = min(a + q, W);
-        total += close_flat<kU, GLOBAL>(P, S, nl, a, b, colO, tab, lg, S + kJL + 64 * kU * w, lane);
+        (void)W;
+        total += close_lists<kQ, kU>(P, S, nl, w, 4, colO, tab, lg, lane);
         __syncthreads();
     }
     total = wave_sum(total);
@@ -816,8 +761,8 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
                   (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
         int32_t dcap = 64;
         while (dcap < dmax_large) dcap <<= 1;
-        // tab: next_pow2(2d) <= 2*dcap slots, P: kJL+1, S: kJL, marks: 4*64*kU
-        const size_t per_block = (size_t)(2 * dcap + 2 * kJL + 1 + 256 * kU);
+        // tab: next_pow2(2d) <= 2*dcap slots, P: kJL+1, S: kJL
+        const size_t per_block = (size_t)(2 * dcap + 2 * kJL + 1);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
         int64_t blocks = (int64_t)num_cus() * (lds_bytes <= 20 * 1024 ? 8 : lds_bytes <= 40 * 1024 ? 4 : 2);
         if (blocks > n_large) blocks = n_large;
