@@ -146,7 +146,7 @@ tc_status tc_rp_trace(tc_graph g, int32_t k, uint64_t seed, void* stream, int64_
    changes the reported light/heavy split). */
 typedef struct {
     int32_t heavy_num, heavy_den; /* heavy iff heavy_den^2 deg^2 > heavy_num^2 m */
-    int32_t small_dmax;           /* anchors with out-degree <= this use one wave per item (1..256) */
+    int32_t small_dmax;           /* anchors with out-degree <= this use one wave per item (1..128) */
     int32_t vmajor_cap;           /* pairs (u,v) with d+(u) <= d+(v) <= cap are closed from v's side;
                                      0 closes every pair from u's side */
     int32_t blocks_per_cu;        /* persistent grid of the wave-per-item kernel (1..16) */
@@ -159,7 +159,7 @@ tc_status tc_tune_set(tc_graph g, double p, const tc_tuning* t);
 tc_status tc_tune_get(tc_graph g, double p, tc_tuning* t);
 
 /* Time every candidate of a fixed grid (vmajor_cap in {0, 1024},
-   small_dmax in {128, 256}, and, if search_heavy, the heavy multiplier in
+   small_dmax in {64, 128}, and, if search_heavy, the heavy multiplier in
    {1/2, 1, 2}; else the multiplier of the stored entry or 1) on the graph
    sampled with (p, seed), store the fastest and return it in *best (may be
    NULL).  Counts of all candidates must agree; TC_ERR_DEVICE otherwise. */

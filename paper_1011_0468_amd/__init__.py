@@ -142,7 +142,7 @@ def tc_rp_trace(g, k, seed, stream=None):
     return q, est.value
 
 
-def tc_tune_set(g, p, heavy=(1, 1), small_dmax=256, vmajor_cap=1024, blocks_per_cu=8):
+def tc_tune_set(g, p, heavy=(1, 1), small_dmax=128, vmajor_cap=1024, blocks_per_cu=8):
     t = TcTuning(int(heavy[0]), int(heavy[1]), int(small_dmax), int(vmajor_cap), int(blocks_per_cu))
     check(_native.load().tc_tune_set(g.handle, float(p), ctypes.byref(t)))
 

@@ -476,7 +476,7 @@ tc_status tc_rp_trace(tc_graph g, int32_t k, uint64_t seed, void* stream, int64_
 static CountConfig from_tuning(const tc_tuning* t) {
     CountConfig c;
     if (t->heavy_den < 1 || t->heavy_num < 0) fail(TC_ERR_INVALID, "heavy_num must be >= 0 and heavy_den >= 1");
-    if (t->small_dmax < 1 || t->small_dmax > 256) fail(TC_ERR_INVALID, "small_dmax must be in [1, 256]");
+    if (t->small_dmax < 1 || t->small_dmax > 128) fail(TC_ERR_INVALID, "small_dmax must be in [1, 128]");
     if (t->vmajor_cap < 0) fail(TC_ERR_INVALID, "vmajor_cap must be >= 0");
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 16) fail(TC_ERR_INVALID, "blocks_per_cu must be in [1, 16]");
     c.heavy_num = t->heavy_num;

@@ -53,8 +53,7 @@ int num_cus() {
 
 // Entries of an iterated list processed by one work item.
 constexpr int kJL = 256;
-// Lanes per streamed list, and loads in flight per lane, in the closure loop.
-constexpr int kQ = 16;
+// Strips of 64 positions per super-strip of the closure loop.
 constexpr int kU = 4;
 
 // ---------------------------------------------------------------------------
@@ -292,25 +291,30 @@ __device__ __forceinline__ uint32_t hslot(int32_t w, int lg) {
     return prod >> (32 - lg);
 }
 
+// The anchor's out-list is kept in a bucketed open-addressing table: 2^lg
+// buckets of 4 slots (one 16-byte LDS read each), sized so that at most a
+// quarter of the slots are used.  A key goes to the first bucket with a free
+// slot along its probe sequence (home bucket, then the next ones); slots only
+// ever change from empty (-1) to full, so a lookup can stop at the first
+// bucket that holds the key or an empty slot.
 __device__ __forceinline__ void hash_insert(int32_t* tab, int lg, int32_t v) {
     const uint32_t mask = (1u << lg) - 1;
-    uint32_t s = hslot(v, lg) & mask;
+    uint32_t bk = hslot(v, lg) & mask;
     while (true) {
-        const int32_t prev = atomicCAS(&tab[s], -1, v);
-        if (prev == -1 || prev == v) break;
-        s = (s + 1) & mask;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int32_t prev = atomicCAS(&tab[4 * bk + s], -1, v);
+            if (prev == -1 || prev == v) return;
+        }
+        bk = (bk + 1) & mask;
     }
 }
 
-__device__ __forceinline__ int hash_contains(const int32_t* tab, int lg, int32_t w) {
-    const uint32_t mask = (1u << lg) - 1;
-    uint32_t s = hslot(w, lg) & mask;
-    while (true) {
-        const int32_t k = tab[s];
-        if (k == w) return 1;
-        if (k == -1) return 0;
-        s = (s + 1) & mask;
-    }
+// Buckets for a table that holds d keys at load <= 1/4: 2^lg >= d, at least 16.
+__device__ __forceinline__ int bucket_bits(int32_t d) {
+    int lg = 4;
+    while ((1 << lg) < d) ++lg;
+    return lg;
 }
 
 // largest j in [0, d-1] with P[j] <= g  (P non-decreasing, P[0] = 0 <= g)
@@ -339,61 +343,123 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ void wave_lds_sync() { wave_sync<false>(); }
 
-// Membership tests of up to U keys (x[k] < 0: no key) against the hash set,
-// with the U probe sequences advanced together so that every step issues U
-// independent LDS reads.  Returns the number of keys found.
+// Membership tests of up to U keys (x[k] < 0: no key) against the bucketed
+// table: one 16-byte read per key resolves it unless the bucket is full
+// without it; the few unresolved keys continue bucket by bucket.
 template <int U>
 __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const int32_t (&x)[U]) {
     const uint32_t mask = (1u << lg) - 1;
-    uint32_t sl[U];
-    uint32_t live = 0;
+    const int4* t4 = reinterpret_cast<const int4*>(tab);
+    uint32_t bk[U];
     int32_t found = 0;
+    uint32_t live = 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) bk[k] = hslot(x[k] >= 0 ? x[k] : 0, lg) & mask;
+    int4 e[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) e[k] = t4[bk[k]];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-        sl[k] = x[k] >= 0 ? (hslot(x[k], lg) & mask) : 0u;
-        live |= (x[k] >= 0 ? 1u : 0u) << k;
+        const int32_t v = x[k];
+        const bool hit = e[k].x == v || e[k].y == v || e[k].z == v || e[k].w == v;
+        const bool open = (e[k].x | e[k].y | e[k].z | e[k].w) < 0;  // ids are >= 0, empty slots are -1
+        found += (v >= 0 && hit) ? 1 : 0;
+        live |= (v >= 0 && !hit && !open ? 1u : 0u) << k;
     }
-    while (live) {
-        int32_t key[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) key[k] = ((live >> k) & 1u) ? tab[sl[k]] : -1;
+    while (live) {  // rare: home bucket full without the key
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             if (!((live >> k) & 1u)) continue;
-            if (key[k] == x[k]) { ++found; live &= ~(1u << k); }
-            else if (key[k] == -1) live &= ~(1u << k);
-            else sl[k] = (sl[k] + 1) & mask;
+            bk[k] = (bk[k] + 1) & mask;
+            const int4 f = t4[bk[k]];
+            const int32_t v = x[k];
+            if (f.x == v || f.y == v || f.z == v || f.w == v) { ++found; live &= ~(1u << k); }
+            else if ((f.x | f.y | f.z | f.w) < 0) live &= ~(1u << k);
         }
     }
     return found;
 }
 
-// Closure tests for the staged lists j = j0, j0 + jstride, ... (< nl): list j
-// is N+ of one neighbour, starting at colO[S[j]] with P[j+1] - P[j] entries.
-// Each Q-lane sub-group of the wave streams one list at a time (sub-group s of
-// the wave takes every (64/Q)-th of the lists given), Q * U entries per step
-// with U loads per lane issued before the probes.  No cross-lane
-// communication: lanes only share the read-only tables.
-template <int Q, int U>
-__device__ __forceinline__ int32_t close_lists(const int32_t* P, const int32_t* S, int nl, int j0, int jstride,
-                                               const int32_t* __restrict__ colO, const int32_t* tab, int lg,
-                                               int lane) {
-    constexpr int G = 64 / Q;
-    const int sub = lane / Q;
-    const int q = lane % Q;
-    int32_t cnt = 0;
-    for (int j = j0 + sub * jstride; j < nl; j += G * jstride) {
-        const int32_t len = P[j + 1] - P[j];
-        const int32_t base = S[j];
-        for (int32_t off = q; off < len; off += Q * U) {
-            int32_t x[U];
+// Owners and gathers of one super-strip of 64 * U positions starting at g0
+// (< b): position g lies in list j (P[j] <= g < P[j+1]) at offset g - P[j] of
+// the list starting at colO[S[j]]; nl lists, none empty, so P is strictly
+// increasing.  jlo is the owner of g0 on entry (of g0 + 64U - 1 on exit).
+// When the whole super-strip lies in list jlo every lane owns jlo; otherwise
+// the lists starting inside it (at most 64U, those after jlo) are marked at
+// their start offsets in `mark` (64U ints of per-wave LDS) and each lane's
+// owner is the running maximum of the marks: one 64-lane max-scan per strip.
+// Loads are issued for every lane (clamped to the owner's first entry past b)
+// so the caller can keep them in flight.  Whole wave.
+template <int U, bool GLOBAL>
+__device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* S, int nl, int32_t g0, int32_t b,
+                                              const int32_t* __restrict__ colO, int32_t* mark, int lane, int& jlo,
+                                              int32_t (&x)[U]) {
+    int32_t o[U];
+    const int32_t nxt = jlo + 1 < nl ? P[jlo + 1] : INT32_MAX;
+    if (nxt >= g0 + 64 * U) {  // wave-uniform: one list covers the super-strip
+#pragma unroll
+        for (int k = 0; k < U; ++k) o[k] = jlo;
+    } else {
+#pragma unroll
+        for (int k = 0; k < U; ++k) mark[lane + 64 * k] = -1;
+        wave_sync<GLOBAL>();
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int j = jlo + 1 + lane + 64 * k;
+            if (j < nl) {
+                const int32_t off = P[j] - g0;  // >= 0: list jlo + 1 starts after position g0 - 1
+                if (off < 64 * U) mark[off] = j;
+            }
+        }
+        wave_sync<GLOBAL>();
+#pragma unroll
+        for (int k = 0; k < U; ++k) o[k] = mark[lane + 64 * k];
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
 #pragma unroll
             for (int k = 0; k < U; ++k) {
-                const int32_t o = off + Q * k;
-                x[k] = o < len ? colO[base + o] : -1;
+                const int32_t q = __shfl_up(o[k], dd, 64);
+                if (lane >= dd) o[k] = q > o[k] ? q : o[k];
             }
-            cnt += probe_many<U>(tab, lg, x);
         }
+        int32_t carry = jlo;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            o[k] = o[k] > carry ? o[k] : carry;
+            carry = __shfl(o[k], 63, 64);
+        }
+        jlo = carry;
+        wave_sync<GLOBAL>();  // mark reads done before the next super-strip resets it
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const int32_t g = g0 + lane + 64 * k;
+        const int32_t off = g < b ? g - P[o[k]] : 0;
+        const int32_t v = colO[S[o[k]] + off];
+        x[k] = g < b ? v : -1;
+    }
+}
+
+// Closure tests for positions [a, b) of the concatenated streamed lists
+// (layout as in gather_strips).  Software-pipelined: the gathers of the next
+// super-strip are issued before the hash probes of the current one.
+template <int U, bool GLOBAL>
+__device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* S, int nl, int32_t a, int32_t b,
+                                              const int32_t* __restrict__ colO, const int32_t* tab, int lg,
+                                              int32_t* mark, int lane) {
+    int32_t cnt = 0;
+    if (a >= b) return 0;
+    int jlo = find_list(P, nl, a);
+    int32_t xc[U], xn[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) xn[k] = -1;
+    gather_strips<U, GLOBAL>(P, S, nl, a, b, colO, mark, lane, jlo, xc);
+    for (int32_t g0 = a; g0 < b; g0 += 64 * U) {
+        const int32_t gn = g0 + 64 * U;
+        if (gn < b) gather_strips<U, GLOBAL>(P, S, nl, gn, b, colO, mark, lane, jlo, xn);
+        cnt += probe_many<U>(tab, lg, xc);
+#pragma unroll
+        for (int k = 0; k < U; ++k) xc[k] = xn[k];
     }
     return cnt;
 }
@@ -487,13 +553,15 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
                                                       const int32_t* __restrict__ rpD, const int32_t* __restrict__ colD,
                                                       const int32_t* __restrict__ code, int32_t vcap,
                                                       int64_t* __restrict__ acc) {
-    constexpr int HS_MAX = 2 * DS;
-    __shared__ int32_t lds[4][HS_MAX + 2 * kJL + 1];
+    constexpr int HS_MAX = 4 * DS;                                     // buckets of 4 slots, load <= 1/4
+    constexpr int ROW = (HS_MAX + 2 * kJL + 1 + 64 * kU + 3) / 4 * 4;  // keeps every row 16-byte aligned
+    __shared__ __attribute__((aligned(16))) int32_t lds[4][ROW];
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
     int32_t* tab = lds[w];
     int32_t* P = tab + HS_MAX;
     int32_t* S = P + kJL + 1;
+    int32_t* mark = S + kJL;
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
     int64_t total = 0;
@@ -509,9 +577,8 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         else { const int32_t ds = rpD[x]; L = colD + ds; llen = rpD[x + 1] - ds; }
         const int32_t j0 = item.y * kJL;
         const int32_t cnt = min(kJL, llen - j0);
-        int lg = 6;
-        while ((1 << lg) < 2 * d) ++lg;
-        const int hs = 1 << lg;
+        const int lg = bucket_bits(d);
+        const int hs = 4 << lg;
         for (int i = lane; i < hs; i += 64) tab[i] = -1;
         if (lane == 0) P[0] = 0;
         wave_lds_sync();
@@ -519,8 +586,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         int32_t W;
         const int32_t nl = stage_lists<64>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, nullptr, lane, &W);
         wave_lds_sync();
-        (void)W;
-        total += close_lists<kQ, kU>(P, S, nl, 0, 1, colO, tab, lg, lane);
+        total += close_flat<kU, false>(P, S, nl, 0, W, colO, tab, lg, mark, lane);
         wave_lds_sync();
     }
     total = wave_sum(total);
@@ -538,13 +604,13 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
                                                       const int32_t* __restrict__ rpD, const int32_t* __restrict__ colD,
                                                       const int32_t* __restrict__ code, int32_t vcap, int32_t dcap,
                                                       int32_t* __restrict__ gscratch, int64_t* __restrict__ acc) {
-    extern __shared__ int32_t dyn[];
+    extern __shared__ __attribute__((aligned(16))) int32_t dyn[];
     __shared__ int32_t red[5];
-    // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL)
-    const int64_t per_block = 2 * (int64_t)dcap + 2 * kJL + 1;
+    // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL), marks (4 x 64 kU)
+    const int64_t per_block = (4 * (int64_t)dcap + 2 * kJL + 1 + 256 * kU + 3) / 4 * 4;
     int32_t* base = GLOBAL ? gscratch + (int64_t)blockIdx.x * per_block : dyn;
     int32_t* tab = base;
-    int32_t* P = base + 2 * dcap;
+    int32_t* P = base + 4 * dcap;
     int32_t* S = P + kJL + 1;
     const int t = threadIdx.x;
     const int w = t >> 6;
@@ -562,9 +628,8 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         else { const int32_t ds = rpD[x]; L = colD + ds; llen = rpD[x + 1] - ds; }
         const int32_t j0 = item.y * kJL;
         const int32_t cnt = min(kJL, llen - j0);
-        int lg = 6;
-        while ((1 << lg) < 2 * d) ++lg;
-        const int hs = 1 << lg;
+        const int lg = bucket_bits(d);
+        const int hs = 4 << lg;
         for (int i = t; i < hs; i += 256) tab[i] = -1;
         if (t == 0) P[0] = 0;
         __syncthreads();
@@ -572,8 +637,10 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         int32_t W;
         const int32_t nl = stage_lists<256>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, red, t, &W);
         __syncthreads();
-        (void)W;
-        total += close_lists<kQ, kU>(P, S, nl, w, 4, colO, tab, lg, lane);
+        const int32_t q = (W + 3) / 4;
+        const int32_t a = min(w * q, W);
+        const int32_t b = min(a + q, W);
+        total += close_flat<kU, GLOBAL>(P, S, nl, a, b, colO, tab, lg, S + kJL + 64 * kU * w, lane);
         __syncthreads();
     }
     total = wave_sum(total);
@@ -675,7 +742,7 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
         return;
     }
     const int64_t NW = (E2 + 63) / 64;
-    if (cfg.small_dmax > 256 || cfg.small_dmax < 1) fail(TC_ERR_INVALID, "small_dmax must be in [1, 256]");
+    if (cfg.small_dmax > 128 || cfg.small_dmax < 1) fail(TC_ERR_INVALID, "small_dmax must be in [1, 128]");
 
     DevBuf<int64_t> acc(kAccN, s);
     fill_i64(acc.get(), 0, kAccN, s);
@@ -750,7 +817,7 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
         int64_t blocks = (int64_t)num_cus() * cfg.light_blocks_per_cu;
         const int64_t need = (n_small + 3) / 4;
         if (blocks > need) blocks = need;
-        TC_LAUNCH("light_small", k_light_small<256>, dim3((unsigned)blocks), dim3(256), 0, s,
+        TC_LAUNCH("light_small", k_light_small<128>, dim3((unsigned)blocks), dim3(256), 0, s,
                   (const int2*)items.get(), n_small, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
                   (const int32_t*)rpD.get(), (const int32_t*)colD.get(), (const int32_t*)code.get(), vcap, acc.get());
     }
@@ -761,8 +828,8 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
                   (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
         int32_t dcap = 64;
         while (dcap < dmax_large) dcap <<= 1;
-        // tab: next_pow2(2d) <= 2*dcap slots, P: kJL+1, S: kJL
-        const size_t per_block = (size_t)(2 * dcap + 2 * kJL + 1);
+        // tab: 4 * next_pow2(d) <= 4 * dcap slots, P: kJL+1, S: kJL, marks: 4*64*kU (16-byte multiple)
+        const size_t per_block = (size_t)((4 * dcap + 2 * kJL + 1 + 256 * kU + 3) / 4 * 4);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
         int64_t blocks = (int64_t)num_cus() * (lds_bytes <= 20 * 1024 ? 8 : lds_bytes <= 40 * 1024 ? 4 : 2);
         if (blocks > n_large) blocks = n_large;

@@ -145,7 +145,7 @@ void compact_kept(const int32_t* col, const int32_t* src, int64_t E2, const uint
 
 struct CountConfig {
     int32_t heavy_num = 1, heavy_den = 1;
-    int32_t small_dmax = 256;        // anchors with d+ <= small_dmax use a wave each, others a block
+    int32_t small_dmax = 128;        // anchors with d+ <= small_dmax use a wave each, others a block
     int32_t vmajor_cap = 1024;       // pairs with d+(u) <= d+(v) <= cap are closed from v's side (0: never)
     int32_t light_blocks_per_cu = 8; // persistent grid of the wave-per-item kernel
 };

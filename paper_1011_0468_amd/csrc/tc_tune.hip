@@ -52,7 +52,7 @@ CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, u
         nh = 1;
     }
     const int32_t caps[2] = {0, 1024};
-    const int32_t dmaxs[2] = {128, 256};
+    const int32_t dmaxs[2] = {64, 128};
     CountConfig best;
     double best_ms = 1e300;
     int64_t T = -1;

@@ -167,8 +167,8 @@ def test_invalid_p_and_groups(gpu):
         gpu.tc_estimate(g, 0.5, [0, 1, 2], num_groups=2)
 
 
-TUNINGS = [dict(vmajor_cap=0, small_dmax=256), dict(vmajor_cap=1024, small_dmax=256),
-           dict(vmajor_cap=4, small_dmax=32), dict(vmajor_cap=1 << 30, small_dmax=256),
+TUNINGS = [dict(vmajor_cap=0, small_dmax=128), dict(vmajor_cap=1024, small_dmax=128),
+           dict(vmajor_cap=4, small_dmax=32), dict(vmajor_cap=1 << 30, small_dmax=128),
            dict(vmajor_cap=1 << 30, small_dmax=1), dict(vmajor_cap=0, small_dmax=1)]
 
 
