@@ -101,7 +101,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0)
-    ap.add_argument("--no-tune", action="store_true", help="library defaults instead of autotuned launch parameters")
+    ap.add_argument("--autotune", action="store_true",
+                    help="search launch parameters per operating point before timing (default: library defaults)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -130,11 +131,13 @@ def main():
     del src, dst
     info = g.info()
 
-    tuned = not args.no_tune
+    tuned = args.autotune
     tunings = {}
-    if tuned:  # untimed: pick launch parameters per operating point; the threshold stays deg <= sqrt(m')
-        for p in ps:
+    for p in ps:
+        if tuned:  # untimed: pick launch parameters per operating point; the threshold stays deg <= sqrt(m')
             tunings[str(p)] = tc.tc_autotune(g, p, seed=args.seed, search_heavy=False)
+        else:
+            tunings[str(p)] = tc.tc_tune_get(g, p)
 
     def step():
         out = []
