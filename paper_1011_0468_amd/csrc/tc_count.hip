@@ -144,10 +144,15 @@ __device__ __forceinline__ bool run_tail_sum(int32_t key, bool valid, int64_t va
 //   Wu[u] += d+(v) for u-major pairs; gather statistic += d+(v) for every pair.
 // Over down entries (row v, entry u, grouped by v):
 //   Wv[v] += d+(u) for v-major pairs.
+// Every entry also receives, at its own position in `pack`, the list the
+// closure kernels stream for it: (start of N+(y) in the up lists, length), or
+// (0, 0) if the pair is closed from the other side.  The closure kernels then
+// stage an anchor's lists with coalesced reads instead of gathers.
 __global__ void __launch_bounds__(256) k_work(const int32_t* __restrict__ rowE, const int32_t* __restrict__ colE,
                                                const int32_t* __restrict__ mp_dev, const int32_t* __restrict__ code,
-                                               const int32_t* __restrict__ dplus, int32_t vcap, int32_t down,
-                                               int64_t* __restrict__ W, int64_t* __restrict__ acc) {
+                                               const int32_t* __restrict__ rpO, int32_t vcap, int32_t down,
+                                               int64_t* __restrict__ W, int2* __restrict__ pack,
+                                               int64_t* __restrict__ acc) {
     const int64_t mo = mp_dev[0];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t gsum = 0;
@@ -159,17 +164,24 @@ __global__ void __launch_bounds__(256) k_work(const int32_t* __restrict__ rowE, 
         if (e < mo) {
             key = rowE[e];
             const int32_t y = colE[e];
+            int2 pk = make_int2(0, 0);
             if (!down) {
                 const int32_t cu = code[key];
                 if (cu > 0) {
-                    const int32_t dv = dplus[y];
+                    const int32_t sv = rpO[y];
+                    const int32_t dv = rpO[y + 1] - sv;
                     gsum += dv;
-                    if (!vmajor(cu, dv, vcap)) { valid = true; val = dv; }
+                    if (!vmajor(cu, dv, vcap)) { valid = true; val = dv; pk = make_int2(sv, dv); }
                 }
             } else {
                 const int32_t cu = code[y];
-                if (cu > 0 && vmajor(cu, dplus[key], vcap)) { valid = true; val = cu; }
+                if (cu > 0 && vmajor(cu, rpO[key + 1] - rpO[key], vcap)) {
+                    valid = true;
+                    val = cu;
+                    pk = make_int2(rpO[y], cu);
+                }
             }
+            pack[e] = pk;
         }
         int64_t sum;
         const bool tail = run_tail_sum(valid ? key : -1, valid, val, &sum);
@@ -482,38 +494,26 @@ __device__ __forceinline__ void build_hash(int32_t rs, int32_t d, const int32_t*
     }
 }
 
-// Stage the iterated entries L[0..cnt) (cnt <= kJL): for entry y, the streamed
-// list is N+(y) if the pair is closed from this anchor, else nothing.  kind_u:
-// anchor x = u, entries y = v in N+(u); else anchor x = v, entries y = u in
-// N-(v).  Non-empty lists are compacted in entry order into S (start in colO)
-// and P (exclusive prefix of lengths, P[nl] = total).  Returns nl; *total
-// receives the number of positions.
+// Stage the packed entries L[0..cnt) (cnt <= kJL) of an anchor's iterated
+// list: (start in colO, length) of the list streamed for each entry, length 0
+// when the pair is closed from the other side.  Non-empty lists are compacted
+// in entry order into S (start) and P (exclusive prefix of lengths, P[nl] =
+// total).  Returns nl; *total receives the number of positions.
 template <int NT>
-__device__ __forceinline__ int32_t stage_lists(const int32_t* __restrict__ L, int32_t cnt, bool kind_u, int32_t dx,
-                                               int32_t vcap, const int32_t* __restrict__ rpO,
-                                               const int32_t* __restrict__ code, int32_t* P, int32_t* S,
+__device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32_t cnt, int32_t* P, int32_t* S,
                                                int32_t* red, int t, int32_t* total) {
     constexpr int R = (kJL + NT - 1) / NT;
-    int32_t y[R], st[R], ln[R];
+    int32_t st[R], ln[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int j = t * R + k;  // consecutive entries per thread
-        y[k] = j < cnt ? L[j] : -1;
+        const int2 e = j < cnt ? L[j] : make_int2(0, 0);
+        st[k] = e.x;
+        ln[k] = e.y;
     }
     int32_t loc = 0, nloc = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        st[k] = 0;
-        ln[k] = 0;
-        if (y[k] >= 0) {
-            st[k] = rpO[y[k]];
-            const int32_t en = rpO[y[k] + 1];
-            const int32_t dy = en - st[k];
-            bool take;
-            if (kind_u) take = !vmajor(dx, dy, vcap);
-            else { const int32_t cu = code[y[k]]; take = cu > 0 && vmajor(cu, dx, vcap); }
-            ln[k] = take ? dy : 0;
-        }
         loc += ln[k];
         nloc += ln[k] > 0 ? 1 : 0;
     }
@@ -550,9 +550,8 @@ __device__ __forceinline__ int32_t stage_lists(const int32_t* __restrict__ L, in
 template <int DS>
 __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ items, int64_t n_items,
                                                       const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
-                                                      const int32_t* __restrict__ rpD, const int32_t* __restrict__ colD,
-                                                      const int32_t* __restrict__ code, int32_t vcap,
-                                                      int64_t* __restrict__ acc) {
+                                                      const int32_t* __restrict__ rpD, const int2* __restrict__ packU,
+                                                      const int2* __restrict__ packD, int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 4 * DS;                                     // buckets of 4 slots, load <= 1/4
     constexpr int ROW = (HS_MAX + 2 * kJL + 1 + 64 * kU + 3) / 4 * 4;  // keeps every row 16-byte aligned
     __shared__ __attribute__((aligned(16))) int32_t lds[4][ROW];
@@ -571,10 +570,10 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         const int32_t x = kind_u ? item.x : ~item.x;
         const int32_t rs = rpO[x];
         const int32_t d = rpO[x + 1] - rs;
-        const int32_t* L;
+        const int2* L;
         int32_t llen;
-        if (kind_u) { L = colO + rs; llen = d; }
-        else { const int32_t ds = rpD[x]; L = colD + ds; llen = rpD[x + 1] - ds; }
+        if (kind_u) { L = packU + rs; llen = d; }
+        else { const int32_t ds = rpD[x]; L = packD + ds; llen = rpD[x + 1] - ds; }
         const int32_t j0 = item.y * kJL;
         const int32_t cnt = min(kJL, llen - j0);
         const int lg = bucket_bits(d);
@@ -584,7 +583,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         wave_lds_sync();
         build_hash<64>(rs, d, colO, tab, lg, lane);
         int32_t W;
-        const int32_t nl = stage_lists<64>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, nullptr, lane, &W);
+        const int32_t nl = stage_lists<64>(L + j0, cnt, P, S, nullptr, lane, &W);
         wave_lds_sync();
         total += close_flat<kU, false>(P, S, nl, 0, W, colO, tab, lg, mark, lane);
         wave_lds_sync();
@@ -601,8 +600,8 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
 template <bool GLOBAL>
 __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ items, int64_t n_items,
                                                       const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
-                                                      const int32_t* __restrict__ rpD, const int32_t* __restrict__ colD,
-                                                      const int32_t* __restrict__ code, int32_t vcap, int32_t dcap,
+                                                      const int32_t* __restrict__ rpD, const int2* __restrict__ packU,
+                                                      const int2* __restrict__ packD, int32_t dcap,
                                                       int32_t* __restrict__ gscratch, int64_t* __restrict__ acc) {
     extern __shared__ __attribute__((aligned(16))) int32_t dyn[];
     __shared__ int32_t red[5];
@@ -622,10 +621,10 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         const int32_t x = kind_u ? item.x : ~item.x;
         const int32_t rs = rpO[x];
         const int32_t d = rpO[x + 1] - rs;
-        const int32_t* L;
+        const int2* L;
         int32_t llen;
-        if (kind_u) { L = colO + rs; llen = d; }
-        else { const int32_t ds = rpD[x]; L = colD + ds; llen = rpD[x + 1] - ds; }
+        if (kind_u) { L = packU + rs; llen = d; }
+        else { const int32_t ds = rpD[x]; L = packD + ds; llen = rpD[x + 1] - ds; }
         const int32_t j0 = item.y * kJL;
         const int32_t cnt = min(kJL, llen - j0);
         const int lg = bucket_bits(d);
@@ -635,7 +634,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         __syncthreads();
         build_hash<256>(rs, d, colO, tab, lg, t);
         int32_t W;
-        const int32_t nl = stage_lists<256>(L + j0, cnt, kind_u, d, vcap, rpO, code, P, S, red, t, &W);
+        const int32_t nl = stage_lists<256>(L + j0, cnt, P, S, red, t, &W);
         __syncthreads();
         const int32_t q = (W + 3) / 4;
         const int32_t a = min(w * q, W);
@@ -787,11 +786,13 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
     fill_i64(Wu.get(), 0, n, s);
     fill_i64(Wv.get(), 0, n, s);
     const unsigned wgrid = std::min<unsigned>(grid_for(g->m, 256), 8192u);
+    DevBuf<int2> packU(g->m, s), packD(vcap > 0 ? g->m : 1, s);
     TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcO.get(), (const int32_t*)colO.get(),
-              mp_dev, (const int32_t*)code.get(), (const int32_t*)dplus.get(), vcap, 0, Wu.get(), acc.get());
+              mp_dev, (const int32_t*)code.get(), (const int32_t*)rpO.get(), vcap, 0, Wu.get(), packU.get(), acc.get());
     if (vcap > 0)
         TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcD.get(), (const int32_t*)colD.get(),
-                  mp_dev, (const int32_t*)code.get(), (const int32_t*)dplus.get(), vcap, 1, Wv.get(), acc.get());
+                  mp_dev, (const int32_t*)code.get(), (const int32_t*)rpO.get(), vcap, 1, Wv.get(), packD.get(),
+                  acc.get());
     DevBuf<int32_t> nsm(n + 1, s), nlg(n + 1, s);
     TC_LAUNCH("classify", k_classify, dim3(std::min<unsigned>(grid_for(n, 256), 2048u)), dim3(256), 0, s, n,
               (const int32_t*)code.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
@@ -819,7 +820,7 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
         if (blocks > need) blocks = need;
         TC_LAUNCH("light_small", k_light_small<128>, dim3((unsigned)blocks), dim3(256), 0, s,
                   (const int2*)items.get(), n_small, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
-                  (const int32_t*)rpD.get(), (const int32_t*)colD.get(), (const int32_t*)code.get(), vcap, acc.get());
+                  (const int32_t*)rpD.get(), (const int2*)packU.get(), (const int2*)packD.get(), acc.get());
     }
     if (n_large > 0) {
         DevBuf<int2> items(n_large, s);
@@ -842,12 +843,12 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
         if (dyn > 0)
             TC_LAUNCH("light_large", k_light_large<false>, dim3((unsigned)blocks), dim3(256), dyn, s,
                       (const int2*)items.get(), n_large, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
-                      (const int32_t*)rpD.get(), (const int32_t*)colD.get(), (const int32_t*)code.get(), vcap, dcap,
+                      (const int32_t*)rpD.get(), (const int2*)packU.get(), (const int2*)packD.get(), dcap,
                       (int32_t*)nullptr, acc.get());
         else
             TC_LAUNCH("light_large", k_light_large<true>, dim3((unsigned)blocks), dim3(256), 0, s,
                       (const int2*)items.get(), n_large, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
-                      (const int32_t*)rpD.get(), (const int32_t*)colD.get(), (const int32_t*)code.get(), vcap, dcap,
+                      (const int32_t*)rpD.get(), (const int2*)packU.get(), (const int2*)packD.get(), dcap,
                       gscr.get(), acc.get());
     }
 
