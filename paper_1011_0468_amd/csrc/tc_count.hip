@@ -832,7 +832,11 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
         // tab: 4 * next_pow2(d) <= 4 * dcap slots, P: kJL+1, S: kJL, marks: 4*64*kU (16-byte multiple)
         const size_t per_block = (size_t)((4 * dcap + 2 * kJL + 1 + 256 * kU + 3) / 4 * 4);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
-        int64_t blocks = (int64_t)num_cus() * (lds_bytes <= 20 * 1024 ? 8 : lds_bytes <= 40 * 1024 ? 4 : 2);
+        // resident blocks per CU: 160 KB of LDS per CU on gfx950, at most 8 blocks of 4 waves
+        int64_t per_cu = (int64_t)((160 * 1024) / (lds_bytes + 64));
+        if (per_cu > 8) per_cu = 8;
+        if (per_cu < 1) per_cu = 1;
+        int64_t blocks = (int64_t)num_cus() * per_cu;
         if (blocks > n_large) blocks = n_large;
         DevBuf<int32_t> gscr;
         size_t dyn = lds_bytes;
