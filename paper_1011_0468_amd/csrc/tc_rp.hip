@@ -3,11 +3,18 @@
 // Y = sum_l r_l^T A^3 r_l.  Here each r_l is a Rademacher vector x_l (the same
 // mean, E[x_i x_j] = delta_ij) so that q_l = x_l^T A^3 x_l = (A x_l)^T A (A x_l)
 // is an exact integer.  Vectors are processed 64 at a time: one 64-bit hash
-// word per vertex holds the 64 signs of a chunk.
+// word per vertex holds the 64 signs of a chunk, and lane b of a wave owns
+// vector b of the chunk.
 //
-//   rp_bits : word[i] = mix64(mix64(c << 32 | i) ^ salt)          (n words)
-//   rp_spmm : Y[i][b] = sum_{j in N(i)} x_b[j] = deg i - 2 #{j : bit b set}
-//   rp_dot  : q[b]  += Y[i][b] * sum_{j in N(i)} Y[j][b]
+//   rp_bits : word[i] = mix64(mix64(c << 32 | i) ^ salt)                 (n words)
+//   rp_spmm : Y[i][b] = sum_{j in N(i)} x_b[j] = deg i - 2 #{j in N(i) : bit b of word[j]}
+//   rp_dot  : q[b]    = sum over CSR entries (i, j) of Y[i][b] * Y[j][b]
+//
+// Both sweeps are edge-parallel: wave w owns CSR entries [w L, (w+1) L), so a
+// hub row is split over many waves.  rp_dot is a plain sum over entries.  In
+// rp_spmm a row that lies entirely inside one wave's range is stored
+// directly; the partial rows at range boundaries are accumulated atomically
+// into a zeroed Y (the count is additive over any split of the row).
 #include "tc_internal.h"
 #include "tc_device.h"
 
@@ -15,53 +22,90 @@ namespace tc {
 
 namespace {
 
+constexpr int kRpRange = 4096;  // CSR entries per wave
+constexpr int kRpUnroll = 8;    // entries whose loads are issued together
+
 __global__ void k_rp_bits(int64_t n, uint64_t chunk, uint64_t salt, uint64_t* __restrict__ words) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         words[i] = mix64(mix64((chunk << 32) | (uint64_t)i) ^ salt);
 }
 
-// one wave per vertex (grid-stride); lane b owns sign bit b
-__global__ void __launch_bounds__(256) k_rp_spmm(int64_t n, const int32_t* __restrict__ row_ptr,
-                                                  const int32_t* __restrict__ col, const uint64_t* __restrict__ words,
-                                                  int32_t* __restrict__ Y) {
-    __shared__ uint64_t stage[4][64];
-    const int w = threadIdx.x >> 6;
-    const int lane = __lane_id();
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < n; i += nw) {
-        const int32_t b0 = row_ptr[i], b1 = row_ptr[i + 1];
-        int32_t ones = 0;
-        for (int32_t e0 = b0; e0 < b1; e0 += 64) {
-            const int32_t e = e0 + lane;
-            stage[w][lane] = e < b1 ? words[col[e]] : 0ull;
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            const int cnt = min(64, b1 - e0);
-            for (int t = 0; t < cnt; ++t) ones += (int32_t)((stage[w][t] >> lane) & 1ull);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        }
-        Y[i * 64 + lane] = (b1 - b0) - 2 * ones;
-    }
+__device__ __forceinline__ void rp_flush(int32_t i, int32_t cnt, int32_t ones, int64_t e0, int64_t e1,
+                                         const int32_t* __restrict__ row_ptr, int32_t* __restrict__ Y, int lane) {
+    const int32_t val = cnt - 2 * ones;
+    if ((int64_t)row_ptr[i] >= e0 && (int64_t)row_ptr[i + 1] <= e1) Y[(int64_t)i * 64 + lane] = val;
+    else atomicAdd(&Y[(int64_t)i * 64 + lane], val);
 }
 
-__global__ void __launch_bounds__(256) k_rp_dot(int64_t n, const int32_t* __restrict__ row_ptr,
+__global__ void __launch_bounds__(256) k_rp_spmm(int64_t E2, const int32_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ src, const int32_t* __restrict__ col,
+                                                  const uint64_t* __restrict__ words, int32_t* __restrict__ Y) {
+    const int lane = __lane_id();
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t e0 = w * kRpRange;
+    if (e0 >= E2) return;
+    const int64_t e1 = e0 + kRpRange < E2 ? e0 + kRpRange : E2;
+    int32_t cur = src[e0];
+    int32_t cnt = 0, ones = 0;
+    for (int64_t e = e0; e < e1; e += kRpUnroll) {
+        int32_t ii[kRpUnroll];
+        uint64_t ww[kRpUnroll];
+#pragma unroll
+        for (int k = 0; k < kRpUnroll; ++k) {
+            const int64_t ek = e + k;
+            ii[k] = ek < e1 ? src[ek] : -1;
+            ww[k] = ek < e1 ? words[col[ek]] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < kRpUnroll; ++k) {
+            if (ii[k] < 0) break;  // wave-uniform: past the range end
+            if (ii[k] != cur) {
+                rp_flush(cur, cnt, ones, e0, e1, row_ptr, Y, lane);
+                cur = ii[k];
+                cnt = 0;
+                ones = 0;
+            }
+            ++cnt;
+            ones += (int32_t)((ww[k] >> lane) & 1ull);
+        }
+    }
+    rp_flush(cur, cnt, ones, e0, e1, row_ptr, Y, lane);
+}
+
+__global__ void __launch_bounds__(256) k_rp_dot(int64_t E2, const int32_t* __restrict__ src,
                                                  const int32_t* __restrict__ col, const int32_t* __restrict__ Y,
                                                  int64_t* __restrict__ q) {
-    const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
-    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int wv = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t e0 = w * kRpRange;
     int64_t acc = 0;
-    for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < n; i += nw) {
-        const int32_t b0 = row_ptr[i], b1 = row_ptr[i + 1];
-        int64_t z = 0;
-        for (int32_t e = b0; e < b1; ++e) z += Y[(int64_t)col[e] * 64 + lane];
-        acc += (int64_t)Y[i * 64 + lane] * z;
+    if (e0 < E2) {
+        const int64_t e1 = e0 + kRpRange < E2 ? e0 + kRpRange : E2;
+        int32_t cur = -1, ycur = 0;
+        for (int64_t e = e0; e < e1; e += kRpUnroll) {
+            int32_t ii[kRpUnroll], yj[kRpUnroll];
+#pragma unroll
+            for (int k = 0; k < kRpUnroll; ++k) {
+                const int64_t ek = e + k;
+                ii[k] = ek < e1 ? src[ek] : -1;
+                yj[k] = ek < e1 ? Y[(int64_t)col[ek] * 64 + lane] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kRpUnroll; ++k) {
+                if (ii[k] < 0) break;
+                if (ii[k] != cur) {
+                    cur = ii[k];
+                    ycur = Y[(int64_t)cur * 64 + lane];
+                }
+                acc += (int64_t)ycur * (int64_t)yj[k];
+            }
+        }
     }
     __shared__ int64_t red[4][64];
-    red[w][lane] = acc;
+    red[wv][lane] = acc;
     __syncthreads();
-    if (w == 0) {
+    if (wv == 0) {
         const int64_t s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
         if (s) atomicAdd((unsigned long long*)&q[lane], (unsigned long long)s);
     }
@@ -106,16 +150,17 @@ void rp_trace(const tc_graph_s* g, int32_t k, uint64_t seed, hipStream_t s, int6
     DevBuf<int32_t> Y((size_t)n * 64, s);
     DevBuf<int64_t> qd(64, s);
     const int32_t nchunks = (k + 63) / 64;
+    const int64_t waves = (E2 + kRpRange - 1) / kRpRange;
+    const unsigned wblocks = (unsigned)((waves + 3) / 4);
     for (int32_t c = 0; c < nchunks; ++c) {
         fill_i64(qd.get(), 0, 64, s);
+        fill_i32(Y.get(), 0, n * 64, s);
         unsigned blocks = ceil_div(n, 256);
         if (blocks > 65536) blocks = 65536;
         TC_LAUNCH("rp_bits", k_rp_bits, dim3(blocks), dim3(256), 0, s, n, (uint64_t)c, salt, words.get());
-        unsigned wblocks = ceil_div(n, 4);
-        if (wblocks > 65536) wblocks = 65536;
-        TC_LAUNCH("rp_spmm", k_rp_spmm, dim3(wblocks), dim3(256), 0, s, n, (const int32_t*)g->row_ptr,
-                  (const int32_t*)g->col, (const uint64_t*)words.get(), Y.get());
-        TC_LAUNCH("rp_dot", k_rp_dot, dim3(wblocks), dim3(256), 0, s, n, (const int32_t*)g->row_ptr,
+        TC_LAUNCH("rp_spmm", k_rp_spmm, dim3(wblocks), dim3(256), 0, s, E2, (const int32_t*)g->row_ptr,
+                  (const int32_t*)g->src, (const int32_t*)g->col, (const uint64_t*)words.get(), Y.get());
+        TC_LAUNCH("rp_dot", k_rp_dot, dim3(wblocks), dim3(256), 0, s, E2, (const int32_t*)g->src,
                   (const int32_t*)g->col, (const int32_t*)Y.get(), qd.get());
         int64_t hq[64];
         check_hip(hipMemcpyAsync(hq, qd.get(), sizeof(hq), hipMemcpyDeviceToHost, s), "q");

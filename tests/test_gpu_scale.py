@@ -72,3 +72,56 @@ def test_rmat22_split_invariance(gpu, rmat22):
         _log("rmat22: p=0.1 split %d/%d" % (a, b))
         per, _, _ = gpu.tc_estimate(g, 0.1, [0], heavy=(a, b))
         assert per[0]["triangles"] == want["triangles"]
+
+
+def _timed(label, fn):
+    import time
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    _log("%s: %.1f ms" % (label, (time.perf_counter() - t) * 1e3))
+    return out
+
+
+@pytest.fixture(scope="module")
+def rmat24(gpu):
+    import torch
+    n, s, d = synth.workload("rmat24")
+    _log("rmat24: building device CSR")
+    g = gpu.tc_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    synth._CACHE.pop("rmat24", None)
+    return n, g
+
+
+def test_rmat24_rp_sampled_vectors_match_golden(gpu, rmat24):
+    """k = 256 Rademacher vectors on R-MAT scale 24: the q_l the oracle
+    computed one by one (tests/golden/rmat24.json) must match exactly."""
+    n, g = rmat24
+    gold = json.load(open(os.path.join(GOLDEN, "rmat24.json")))
+    assert g.info()["m"] == gold["m"]
+    q, est = _timed("rmat24 rp k=256", lambda: gpu.tc_rp_trace(g, gold["k"], gold["seed"]))
+    for l, v in gold["sampled_q"].items():
+        assert int(q[int(l)]) == v, (l, int(q[int(l)]), v)
+    assert est == float(int(q.sum())) / (6.0 * gold["k"])
+
+
+def test_rmat24_exact_count_matches_golden(gpu, rmat24):
+    n, g = rmat24
+    want = json.load(open(os.path.join(GOLDEN, "rmat24_count.json")))["exact"]
+    got = _timed("rmat24 exact", lambda: gpu.tc_count_exact(g))
+    for k in ("triangles", "light", "heavy", "n_heavy", "m"):
+        assert got[k] == want[k], (k, got[k], want[k])
+
+
+def test_cl20_batched_median_of_means_matches_golden(gpu):
+    import torch
+    gold = json.load(open(os.path.join(GOLDEN, "cl20.json")))
+    n, s, d = synth.workload("cl20")
+    g = gpu.tc_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    per, ests, mom = _timed("cl20 64 seeds", lambda: gpu.tc_estimate(g, gold["p"], gold["seeds"],
+                                                                      num_groups=gold["groups"]))
+    assert [c["triangles"] for c in per] == gold["triangles"]
+    assert mom == gold["median_of_means"]
+    assert gpu.tc_count_exact(g)["triangles"] == gold["exact"]["triangles"]
