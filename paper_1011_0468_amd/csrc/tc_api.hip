@@ -419,6 +419,55 @@ tc_status tc_count_exact(tc_graph g, const tc_params* prm, void* stream, tc_coun
     });
 }
 
+// Side streams for batched work (default priority, created once per device).
+static std::vector<hipStream_t> side_streams(int want) {
+    static std::mutex mu;
+    static std::map<int, std::vector<hipStream_t>> per_dev;
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "get device");
+    std::lock_guard<std::mutex> lk(mu);
+    auto& v = per_dev[dev];
+    while ((int)v.size() < want) {
+        hipStream_t st = nullptr;
+        check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "stream create");
+        v.push_back(st);
+    }
+    return std::vector<hipStream_t>(v.begin(), v.begin() + want);
+}
+
+// Counts of several independent sparsified copies of g, enqueued without host
+// synchronisation round-robin on side streams that start after the caller's
+// stream and join it again; one read-back for the whole batch.
+static void count_batch(const tc_graph_s* g, int sampled, uint64_t thr, const uint64_t* salts, int32_t S,
+                        const CountConfig& cfg, hipStream_t s, std::vector<tc_counts>& res) {
+    res.resize((size_t)S);
+    if (S == 1) {
+        count_core(g, sampled, thr, salts[0], cfg, s, &res[0]);
+        return;
+    }
+    DevBuf<int64_t> accs((size_t)S * kCountSlots, s);
+    const int K = S < 4 ? S : 4;
+    std::vector<hipStream_t> side = side_streams(K);
+    hipEvent_t start = nullptr;
+    check_hip(hipEventCreateWithFlags(&start, hipEventDisableTiming), "event");
+    check_hip(hipEventRecord(start, s), "event record");
+    for (int k = 0; k < K; ++k) check_hip(hipStreamWaitEvent(side[(size_t)k], start, 0), "wait");
+    for (int32_t i = 0; i < S; ++i)
+        count_enqueue(g, sampled, thr, salts[i], cfg, side[(size_t)(i % K)], accs.get() + (size_t)i * kCountSlots);
+    std::vector<hipEvent_t> done((size_t)K);
+    for (int k = 0; k < K; ++k) {
+        check_hip(hipEventCreateWithFlags(&done[(size_t)k], hipEventDisableTiming), "event");
+        check_hip(hipEventRecord(done[(size_t)k], side[(size_t)k]), "event record");
+        check_hip(hipStreamWaitEvent(s, done[(size_t)k], 0), "wait");
+    }
+    std::vector<int64_t> h((size_t)S * kCountSlots);
+    check_hip(hipMemcpyAsync(h.data(), accs.get(), sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, s), "acc");
+    check_hip(hipStreamSynchronize(s), "sync");
+    (void)hipEventDestroy(start);
+    for (auto e : done) (void)hipEventDestroy(e);
+    for (int32_t i = 0; i < S; ++i) counts_from_slots(h.data() + (size_t)i * kCountSlots, &res[(size_t)i]);
+}
+
 tc_status tc_estimate(tc_graph g, double p, const uint64_t* seeds, int32_t num_seeds, int32_t num_groups,
                       const tc_params* prm, void* stream, tc_counts* per_seed, double* per_seed_est,
                       double* mom_est) {
@@ -431,9 +480,10 @@ tc_status tc_estimate(tc_graph g, double p, const uint64_t* seeds, int32_t num_s
         const int sampled = p < 1.0 ? 1 : 0;  // p = 1 keeps every edge: the exact count itself
         CountConfig cfg = config_from(prm, g, sampled, p);
         const uint64_t thr = keep_threshold(p);
-        std::vector<tc_counts> res((size_t)num_seeds);
-        for (int32_t i = 0; i < num_seeds; ++i)
-            count_core(g, sampled, thr, sample_salt(seeds[i]), cfg, (hipStream_t)stream, &res[(size_t)i]);
+        std::vector<uint64_t> salts((size_t)num_seeds);
+        for (int32_t i = 0; i < num_seeds; ++i) salts[(size_t)i] = sample_salt(seeds[i]);
+        std::vector<tc_counts> res;
+        count_batch(g, sampled, thr, salts.data(), num_seeds, cfg, (hipStream_t)stream, res);
         if (per_seed)
             for (int32_t i = 0; i < num_seeds; ++i) per_seed[i] = res[(size_t)i];
         if (per_seed_est)

@@ -22,6 +22,7 @@
 #include "tc_device.h"
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 namespace tc {
@@ -30,8 +31,9 @@ namespace {
 
 enum Acc {
     kTL = 0, kTH, kLightSources, kLightOut, kWedges, kGather, kProbes, kDmaxLarge, kBytesSmall, kBytesLarge,
-    kItemsSmall, kItemsLarge, kAccN
+    kItemsSmall, kItemsLarge, kMp, kH, kAccN
 };
+static_assert(kAccN <= kCountSlots, "count result slots");
 
 unsigned grid_for(int64_t N, int threads) {
     unsigned b = ceil_div(N, threads);
@@ -53,6 +55,8 @@ int num_cus() {
 
 // Entries of an iterated list processed by one work item.
 constexpr int kJL = 256;
+// Largest anchor out-degree whose table the block kernel keeps in LDS.
+constexpr int kLdsDcap = 1024;
 // Strips of 64 positions per super-strip of the closure loop.
 constexpr int kU = 4;
 
@@ -212,7 +216,8 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
                                                    const int32_t* __restrict__ dplus, const int32_t* __restrict__ dminus,
                                                    const int64_t* __restrict__ Wu, const int64_t* __restrict__ Wv,
                                                    int32_t small_dmax, int32_t* __restrict__ nsm,
-                                                   int32_t* __restrict__ nlg, int64_t* __restrict__ acc) {
+                                                   int32_t* __restrict__ nlg, int32_t* __restrict__ nhg,
+                                                   int64_t* __restrict__ acc) {
     int64_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sources, out, wedges, probes, bytes_s, bytes_l, items_s, items_l
     int64_t dmax = 0;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
@@ -226,10 +231,12 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
                               (wv > 0 ? 16 * (int64_t)dminus[x] : 0) + 4 * (wu + wv);
         st[3] += wu + wv;
         const bool small = dp <= small_dmax;
-        if (small) { nsm[x] = cu + cv; nlg[x] = 0; st[4] += bytes; st[6] += cu + cv; }
+        const bool huge = dp > kLdsDcap;
+        nsm[x] = small ? cu + cv : 0;
+        nlg[x] = (!small && !huge) ? cu + cv : 0;
+        nhg[x] = huge ? cu + cv : 0;
+        if (small) { st[4] += bytes; st[6] += cu + cv; }
         else {
-            nsm[x] = 0;
-            nlg[x] = cu + cv;
             st[5] += bytes;
             st[7] += cu + cv;
             if (cu + cv > 0) dmax = dp > dmax ? dp : dmax;
@@ -279,14 +286,20 @@ __global__ void k_heavy_list(int64_t n, const int32_t* __restrict__ heavy, const
         if (heavy[x]) hlist[hpos[x]] = (int32_t)x;
 }
 
-__global__ void k_info(const int32_t* mp, const int32_t* sb, const int32_t* lb, const int32_t* hp, const int64_t* acc,
-                       int64_t* info) {
+// zero the first round32(h)^2 bytes of U and UT (h from device)
+__global__ void k_heavy_zero(const int32_t* __restrict__ h_dev, uint8_t* __restrict__ U, uint8_t* __restrict__ UT) {
+    const int64_t hp = ((int64_t)h_dev[0] + 31) / 32 * 32;
+    const int64_t nw = hp * hp / 16;  // 16-byte words (hp is a multiple of 32)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (int64_t)gridDim.x * blockDim.x) {
+        reinterpret_cast<int4*>(U)[i] = make_int4(0, 0, 0, 0);
+        reinterpret_cast<int4*>(UT)[i] = make_int4(0, 0, 0, 0);
+    }
+}
+
+__global__ void k_finish(const int32_t* mp, const int32_t* hp, int64_t* acc) {
     if (threadIdx.x == 0) {
-        info[0] = mp[0];
-        info[1] = sb[0];
-        info[2] = lb[0];
-        info[3] = hp[0];
-        info[4] = acc[kDmaxLarge];
+        acc[kMp] = mp[0];
+        acc[kH] = hp[0];
     }
 }
 
@@ -548,7 +561,8 @@ __device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32
 // (x, r): anchor x, kind u (x >= 0) or v (encoded ~x), entries r*kJL.. of the
 // iterated list.  LDS per wave: hash (2*DS slots), P (kJL+1), S (kJL).
 template <int DS>
-__global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ items, int64_t n_items,
+__global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ items,
+                                                      const int32_t* __restrict__ n_items_dev,
                                                       const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
                                                       const int32_t* __restrict__ rpD, const int2* __restrict__ packU,
                                                       const int2* __restrict__ packD, int64_t* __restrict__ acc) {
@@ -563,6 +577,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
     int32_t* mark = S + kJL;
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t n_items = n_items_dev[0];
     int64_t total = 0;
     for (int64_t it = gw; it < n_items; it += nw) {
         const int2 item = items[it];
@@ -598,7 +613,8 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
 // scratch slice per block when they do not fit (GLOBAL = true).  After
 // staging, each wave closes a quarter of the item's positions.
 template <bool GLOBAL>
-__global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ items, int64_t n_items,
+__global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ items,
+                                                      const int32_t* __restrict__ n_items_dev,
                                                       const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
                                                       const int32_t* __restrict__ rpD, const int2* __restrict__ packU,
                                                       const int2* __restrict__ packD, int32_t dcap,
@@ -614,6 +630,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
     const int t = threadIdx.x;
     const int w = t >> 6;
     const int lane = __lane_id();
+    const int64_t n_items = n_items_dev[0];
     int64_t total = 0;
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = items[it];
@@ -651,10 +668,12 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
 // ---------------------------------------------------------------------------
 
 // rank of each heavy vertex in (deg, id) order, by counting smaller keys
-__global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ hlist, int32_t h,
+__global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev,
                                                      const int32_t* __restrict__ degp, int32_t* __restrict__ hidx,
                                                      int32_t* __restrict__ horder) {
     __shared__ int32_t kd[256], kx[256];
+    const int32_t h = h_dev[0];
+    if ((int64_t)blockIdx.x * 256 >= h) return;  // block-uniform
     const int i = blockIdx.x * 256 + threadIdx.x;
     int32_t x = -1, dx = 0;
     if (i < h) { x = hlist[i]; dx = degp[x]; }
@@ -675,10 +694,12 @@ __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ 
 }
 
 // U[i][j] = 1 and UT[j][i] = 1 for every oriented edge between heavy ranks i < j
-__global__ void __launch_bounds__(256) k_heavy_pack(const int32_t* __restrict__ horder, int32_t h,
+__global__ void __launch_bounds__(256) k_heavy_pack(const int32_t* __restrict__ horder, const int32_t* __restrict__ h_dev,
                                                      const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
-                                                     const int32_t* __restrict__ hidx, int32_t hp,
-                                                     uint8_t* __restrict__ U, uint8_t* __restrict__ UT) {
+                                                     const int32_t* __restrict__ hidx, uint8_t* __restrict__ U,
+                                                     uint8_t* __restrict__ UT) {
+    const int32_t h = h_dev[0];
+    const int32_t hp = (h + 31) / 32 * 32;
     const int i = blockIdx.x;
     if (i >= h) return;
     const int32_t x = horder[i];
@@ -698,9 +719,13 @@ typedef int32_t v16i __attribute__((ext_vector_type(16)));
 // of the A tile and column (l mod 32) of the B tile, 16 consecutive k-bytes
 // starting at 16 * (l / 32); the same k-permutation is used for A and B.
 __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ U, const uint8_t* __restrict__ UT,
-                                                     int32_t hp, int64_t ntiles, int64_t* __restrict__ acc) {
-    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= ntiles) return;
+                                                     const int32_t* __restrict__ h_dev, int64_t* __restrict__ acc) {
+    const int32_t h = h_dev[0];
+    if (h < 3) return;
+    const int32_t hp = (h + 31) / 32 * 32;
+    const int64_t nbk = hp / 32;
+    const int64_t ntiles = nbk * (nbk + 1) / 2;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < ntiles; t += (int64_t)gridDim.x * 4) {
     // invert t = J (J + 1) / 2 + I
     int64_t J = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (J * (J + 1) / 2 > t) --J;
@@ -727,24 +752,34 @@ __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ 
     }
     s = wave_sum(s);
     if (lane == 0 && s) atomicAdd((unsigned long long*)&acc[kTH], (unsigned long long)s);
+    }
 }
 
 }  // namespace
 
-void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
-                hipStream_t s, tc_counts* out) {
+// Heavy-vertex bound: heavy vertices have deg > c m'^(1/2) with c = a/b and the
+// degrees sum to 2m', so h < 2 m'^(1/2) / c <= 2 b m^(1/2) / a (all n if a = 0).
+static int64_t heavy_bound(const tc_graph_s* g, int32_t a, int32_t b) {
+    if (a == 0) return g->n;
+    const double hb = 2.0 * (double)b * std::sqrt((double)g->m) / (double)a + 2.0;
+    return hb < (double)g->n ? (int64_t)hb : g->n;
+}
+
+void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
+                   hipStream_t s, int64_t* acc) {
     const int64_t n = g->n;
     const int64_t E2 = 2 * g->m;
-    tc_counts res{};
-    if (n == 0 || E2 == 0) {
-        *out = res;
-        return;
-    }
-    const int64_t NW = (E2 + 63) / 64;
     if (cfg.small_dmax > 128 || cfg.small_dmax < 1) fail(TC_ERR_INVALID, "small_dmax must be in [1, 128]");
+    fill_i64(acc, 0, kCountSlots, s);
+    if (n == 0 || E2 == 0) return;
+    const int64_t NW = (E2 + 63) / 64;
 
-    DevBuf<int64_t> acc(kAccN, s);
-    fill_i64(acc.get(), 0, kAccN, s);
+    // host-side bounds for every launch (no read-back inside a count)
+    const int64_t hmax = heavy_bound(g, cfg.heavy_num, cfg.heavy_den);
+    const int64_t hp_max = (hmax + 31) / 32 * 32;
+    if (hp_max * hp_max > ((int64_t)16 << 30))
+        fail(TC_ERR_OVERFLOW, "heavy block bound exceeds 16 GiB: raise the heavy threshold");
+    const int64_t items_max = 2 * n + E2 / kJL + 2;
 
     // 1. degrees of the counted graph (section 3.1 coin if sampled)
     DevBuf<uint64_t> keep;
@@ -788,102 +823,105 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
     const unsigned wgrid = std::min<unsigned>(grid_for(g->m, 256), 8192u);
     DevBuf<int2> packU(g->m, s), packD(vcap > 0 ? g->m : 1, s);
     TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcO.get(), (const int32_t*)colO.get(),
-              mp_dev, (const int32_t*)code.get(), (const int32_t*)rpO.get(), vcap, 0, Wu.get(), packU.get(), acc.get());
+              mp_dev, (const int32_t*)code.get(), (const int32_t*)rpO.get(), vcap, 0, Wu.get(), packU.get(), acc);
     if (vcap > 0)
         TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcD.get(), (const int32_t*)colD.get(),
-                  mp_dev, (const int32_t*)code.get(), (const int32_t*)rpO.get(), vcap, 1, Wv.get(), packD.get(),
-                  acc.get());
-    DevBuf<int32_t> nsm(n + 1, s), nlg(n + 1, s);
+                  mp_dev, (const int32_t*)code.get(), (const int32_t*)rpO.get(), vcap, 1, Wv.get(), packD.get(), acc);
+    DevBuf<int32_t> nsm(n + 1, s), nlg(n + 1, s), nhg(n + 1, s);
     TC_LAUNCH("classify", k_classify, dim3(std::min<unsigned>(grid_for(n, 256), 2048u)), dim3(256), 0, s, n,
               (const int32_t*)code.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
-              (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), cfg.small_dmax, nsm.get(), nlg.get(), acc.get());
-    DevBuf<int32_t> sbase(n + 1, s), lbase(n + 1, s), hpos(n + 1, s);
+              (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), cfg.small_dmax, nsm.get(), nlg.get(), nhg.get(),
+              acc);
+    DevBuf<int32_t> sbase(n + 1, s), lbase(n + 1, s), hbase(n + 1, s), hpos(n + 1, s);
     scan_exclusive_i32(nsm.get(), sbase.get(), n, s);
     scan_exclusive_i32(nlg.get(), lbase.get(), n, s);
+    scan_exclusive_i32(nhg.get(), hbase.get(), n, s);
     scan_exclusive_i32(heavy.get(), hpos.get(), n, s);
-    DevBuf<int64_t> info(8, s);
-    TC_LAUNCH("info", k_info, dim3(1), dim3(64), 0, s, mp_dev, (const int32_t*)sbase.get() + n,
-              (const int32_t*)lbase.get() + n, (const int32_t*)hpos.get() + n, (const int64_t*)acc.get(), info.get());
-    int64_t hinfo[8] = {0};
-    check_hip(hipMemcpyAsync(hinfo, info.get(), sizeof(int64_t) * 5, hipMemcpyDeviceToHost, s), "info");
-    check_hip(hipStreamSynchronize(s), "sync");
-    const int64_t mp = hinfo[0], n_small = hinfo[1], n_large = hinfo[2], h = hinfo[3], dmax_large = hinfo[4];
 
-    // 4. light phase
-    if (n_small > 0) {
-        DevBuf<int2> items(n_small, s);
+    // 4. light phase: three bins by anchor out-degree; each kernel is a
+    //    persistent grid that reads its item count from device memory
+    const int32_t maxd = g->max_deg;  // bounds every d+ of every sample
+    {
+        DevBuf<int2> items(items_max, s);
         TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)nsm.get(),
                   (const int32_t*)sbase.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
                   (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
-        int64_t blocks = (int64_t)num_cus() * cfg.light_blocks_per_cu;
-        const int64_t need = (n_small + 3) / 4;
-        if (blocks > need) blocks = need;
+        const int64_t blocks = (int64_t)num_cus() * cfg.light_blocks_per_cu;
         TC_LAUNCH("light_small", k_light_small<128>, dim3((unsigned)blocks), dim3(256), 0, s,
-                  (const int2*)items.get(), n_small, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
-                  (const int32_t*)rpD.get(), (const int2*)packU.get(), (const int2*)packD.get(), acc.get());
+                  (const int2*)items.get(), (const int32_t*)sbase.get() + n, (const int32_t*)rpO.get(),
+                  (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const int2*)packU.get(),
+                  (const int2*)packD.get(), acc);
     }
-    if (n_large > 0) {
-        DevBuf<int2> items(n_large, s);
-        TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)nlg.get(),
-                  (const int32_t*)lbase.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
+    auto launch_large = [&](const DevBuf<int32_t>& cnt, const DevBuf<int32_t>& base, int32_t dcap, bool global) {
+        DevBuf<int2> items(items_max, s);
+        TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)cnt.get(),
+                  (const int32_t*)base.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
                   (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
-        int32_t dcap = 64;
-        while (dcap < dmax_large) dcap <<= 1;
         // tab: 4 * next_pow2(d) <= 4 * dcap slots, P: kJL+1, S: kJL, marks: 4*64*kU (16-byte multiple)
         const size_t per_block = (size_t)((4 * dcap + 2 * kJL + 1 + 256 * kU + 3) / 4 * 4);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
-        // resident blocks per CU: 160 KB of LDS per CU on gfx950, at most 8 blocks of 4 waves
-        int64_t per_cu = (int64_t)((160 * 1024) / (lds_bytes + 64));
-        if (per_cu > 8) per_cu = 8;
-        if (per_cu < 1) per_cu = 1;
-        int64_t blocks = (int64_t)num_cus() * per_cu;
-        if (blocks > n_large) blocks = n_large;
-        DevBuf<int32_t> gscr;
-        size_t dyn = lds_bytes;
-        if (lds_bytes > 64 * 1024) {
-            gscr.reset((size_t)blocks * per_block, s);
-            dyn = 0;
+        if (!global) {
+            // resident blocks per CU: 160 KB of LDS per CU on gfx950, at most 8 blocks of 4 waves
+            int64_t per_cu = (int64_t)((160 * 1024) / (lds_bytes + 64));
+            if (per_cu > 8) per_cu = 8;
+            if (per_cu < 1) per_cu = 1;
+            const int64_t blocks = (int64_t)num_cus() * per_cu;
+            TC_LAUNCH("light_large", k_light_large<false>, dim3((unsigned)blocks), dim3(256), lds_bytes, s,
+                      (const int2*)items.get(), (const int32_t*)base.get() + n, (const int32_t*)rpO.get(),
+                      (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const int2*)packU.get(),
+                      (const int2*)packD.get(), dcap, (int32_t*)nullptr, acc);
+        } else {
+            const int64_t blocks = (int64_t)num_cus();
+            DevBuf<int32_t> gscr((size_t)blocks * per_block, s);
+            TC_LAUNCH("light_huge", k_light_large<true>, dim3((unsigned)blocks), dim3(256), 0, s,
+                      (const int2*)items.get(), (const int32_t*)base.get() + n, (const int32_t*)rpO.get(),
+                      (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const int2*)packU.get(),
+                      (const int2*)packD.get(), dcap, gscr.get(), acc);
         }
-        if (dyn > 0)
-            TC_LAUNCH("light_large", k_light_large<false>, dim3((unsigned)blocks), dim3(256), dyn, s,
-                      (const int2*)items.get(), n_large, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
-                      (const int32_t*)rpD.get(), (const int2*)packU.get(), (const int2*)packD.get(), dcap,
-                      (int32_t*)nullptr, acc.get());
-        else
-            TC_LAUNCH("light_large", k_light_large<true>, dim3((unsigned)blocks), dim3(256), 0, s,
-                      (const int2*)items.get(), n_large, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
-                      (const int32_t*)rpD.get(), (const int2*)packU.get(), (const int2*)packD.get(), dcap,
-                      gscr.get(), acc.get());
+    };
+    if (maxd > cfg.small_dmax) {
+        int32_t dcap = 64;
+        while (dcap < std::min<int32_t>(maxd, kLdsDcap)) dcap <<= 1;
+        launch_large(nlg, lbase, dcap, false);
+    }
+    if (maxd > kLdsDcap) {
+        // anchors of this bin: light sources (d+ <= deg <= c m'^(1/2) <= c m^(1/2)) or
+        // v-side anchors (d+ <= vmajor_cap)
+        const double light_cap = cfg.heavy_num == 0 ? 0.0
+                                 : (double)cfg.heavy_num * std::sqrt((double)g->m) / (double)cfg.heavy_den + 1.0;
+        int64_t dbound = std::max<int64_t>((int64_t)vcap, (int64_t)std::min(light_cap, (double)maxd));
+        dbound = std::min<int64_t>(dbound, maxd);
+        int32_t dcap = 64;
+        while (dcap < dbound) dcap <<= 1;
+        if (dbound > kLdsDcap) launch_large(nhg, hbase, dcap, true);
     }
 
-    // 5. heavy phase
-    if (h >= 3) {
-        DevBuf<int32_t> hlist(h, s), hidx(n, s), horder(h, s);
+    // 5. heavy phase: sized by the bound, trimmed to the device's h inside the kernels
+    if (hmax >= 3) {
+        DevBuf<int32_t> hlist(hmax, s), hidx(n, s), horder(hmax, s);
+        const int32_t* h_dev = hpos.get() + n;
         TC_LAUNCH("heavy_list", k_heavy_list, dim3(grid_for(n, 256)), dim3(256), 0, s, n,
                   (const int32_t*)heavy.get(), (const int32_t*)hpos.get(), hlist.get());
-        TC_LAUNCH("heavy_rank", k_heavy_rank, dim3(ceil_div(h, 256)), dim3(256), 0, s, (const int32_t*)hlist.get(),
-                  (int32_t)h, degp, hidx.get(), horder.get());
-        const int32_t hp = (int32_t)((h + 31) / 32 * 32);
-        DevBuf<uint8_t> U((size_t)hp * hp, s), UT((size_t)hp * hp, s);
-        fill_u8(U.get(), 0, (int64_t)hp * hp, s);
-        fill_u8(UT.get(), 0, (int64_t)hp * hp, s);
-        TC_LAUNCH("heavy_pack", k_heavy_pack, dim3((unsigned)h), dim3(256), 0, s, (const int32_t*)horder.get(),
-                  (int32_t)h, (const int32_t*)rpO.get(), (const int32_t*)colO.get(), (const int32_t*)hidx.get(), hp,
-                  U.get(), UT.get());
-        const int64_t nb = hp / 32;
-        const int64_t ntiles = nb * (nb + 1) / 2;
-        TC_LAUNCH("heavy_mfma", k_heavy_mfma, dim3(ceil_div(ntiles, 4)), dim3(256), 0, s, (const uint8_t*)U.get(),
-                  (const uint8_t*)UT.get(), hp, ntiles, acc.get());
+        TC_LAUNCH("heavy_rank", k_heavy_rank, dim3(ceil_div(hmax, 256)), dim3(256), 0, s, (const int32_t*)hlist.get(),
+                  h_dev, degp, hidx.get(), horder.get());
+        DevBuf<uint8_t> U((size_t)hp_max * hp_max, s), UT((size_t)hp_max * hp_max, s);
+        TC_LAUNCH("heavy_zero", k_heavy_zero, dim3(2048), dim3(256), 0, s, h_dev, U.get(), UT.get());
+        TC_LAUNCH("heavy_pack", k_heavy_pack, dim3((unsigned)hmax), dim3(256), 0, s, (const int32_t*)horder.get(),
+                  h_dev, (const int32_t*)rpO.get(), (const int32_t*)colO.get(), (const int32_t*)hidx.get(), U.get(),
+                  UT.get());
+        TC_LAUNCH("heavy_mfma", k_heavy_mfma, dim3((unsigned)(num_cus() * 8)), dim3(256), 0, s,
+                  (const uint8_t*)U.get(), (const uint8_t*)UT.get(), h_dev, acc);
     }
+    TC_LAUNCH("finish", k_finish, dim3(1), dim3(64), 0, s, mp_dev, (const int32_t*)hpos.get() + n, acc);
+}
 
-    int64_t hacc[kAccN];
-    check_hip(hipMemcpyAsync(hacc, acc.get(), sizeof(hacc), hipMemcpyDeviceToHost, s), "acc");
-    check_hip(hipStreamSynchronize(s), "sync");
+void counts_from_slots(const int64_t* hacc, tc_counts* out) {
+    tc_counts res{};
     res.light = hacc[kTL];
     res.heavy = hacc[kTH];
     res.triangles = res.light + res.heavy;
-    res.m = mp;
-    res.n_heavy = h;
+    res.m = hacc[kMp];
+    res.n_heavy = hacc[kH];
     res.light_sources = hacc[kLightSources];
     res.light_out_edges = hacc[kLightOut];
     res.wedges = hacc[kWedges];
@@ -894,6 +932,16 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
     res.model_bytes_small = hacc[kBytesSmall];
     res.model_bytes_large = hacc[kBytesLarge];
     *out = res;
+}
+
+void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
+                hipStream_t s, tc_counts* out) {
+    DevBuf<int64_t> acc(kCountSlots, s);
+    count_enqueue(g, sampled, thr, salt, cfg, s, acc.get());
+    int64_t hacc[kCountSlots];
+    check_hip(hipMemcpyAsync(hacc, acc.get(), sizeof(hacc), hipMemcpyDeviceToHost, s), "acc");
+    check_hip(hipStreamSynchronize(s), "sync");
+    counts_from_slots(hacc, out);
 }
 
 }  // namespace tc

@@ -150,7 +150,16 @@ struct CountConfig {
     int32_t light_blocks_per_cu = 8; // persistent grid of the wave-per-item kernel
 };
 
-// Exact count of the graph, or of its copy sampled with (thr, salt) if sampled != 0.
+// Device result slots of one count (int64 each).
+constexpr int kCountSlots = 16;
+
+// Enqueue the exact count of the graph, or of its copy sampled with (thr, salt)
+// if sampled != 0, on stream s without any host synchronisation; the result
+// lands in acc[kCountSlots] (device).  Launch sizes come from host-side bounds.
+void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
+                   hipStream_t s, int64_t* acc);
+void counts_from_slots(const int64_t* hacc, tc_counts* out);
+// count_enqueue + read-back (synchronises s).
 void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
                 hipStream_t s, tc_counts* out);
 
