@@ -67,16 +67,21 @@ constexpr int kU = 4;
 // Per CSR entry (u, v) of a kept edge: "up" if (deg u, u) < (deg v, v), else
 // "down".  Each kept undirected edge has exactly one up entry (in the row of
 // its lower-ranked end) and one down entry (in the row of its higher end).
+// E2 bounds the buffers; E2_dev (if not null) holds the number of valid
+// entries, which may be smaller (a compacted sample in buffers sized for the
+// full graph): words past it get zero bits.
 __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__ src, const int32_t* __restrict__ col,
-                                                      int64_t E2, const uint64_t* __restrict__ keep,
+                                                      int64_t E2, const int32_t* __restrict__ E2_dev,
+                                                      const uint64_t* __restrict__ keep,
                                                       const int32_t* __restrict__ degp, uint64_t* __restrict__ ubits,
                                                       int32_t* __restrict__ ucnt, uint64_t* __restrict__ dbits,
                                                       int32_t* __restrict__ dcnt) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t valid = E2_dev ? (int64_t)E2_dev[0] : E2;
     for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < E2; e0 += stride) {
         const int64_t e = e0 + threadIdx.x;
         bool up = false, dn = false;
-        if (e < E2) {
+        if (e < valid) {
             const bool k = keep ? ((keep[e >> 6] >> (e & 63)) & 1ull) : true;
             if (k) {
                 const int32_t u = src[e], v = col[e];
@@ -781,36 +786,49 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         fail(TC_ERR_OVERFLOW, "heavy block bound exceeds 16 GiB: raise the heavy threshold");
     const int64_t items_max = 2 * n + E2 / kJL + 2;
 
-    // 1. degrees of the counted graph (section 3.1 coin if sampled)
-    DevBuf<uint64_t> keep;
-    DevBuf<int32_t> kpre;
-    DevBuf<int32_t> degp_buf;
+    // 1. the counted graph: the input CSR, or its sample compacted into buffers
+    //    sized for the full graph (section 3.1 coin), so that every later pass
+    //    touches m' entries instead of m
+    const int32_t* v_row = g->row_ptr;
+    const int32_t* v_col = g->col;
+    const int32_t* v_src = g->src;
     const int32_t* degp = g->deg;
+    const int32_t* E2_dev = nullptr;
+    DevBuf<uint64_t> keep;
+    DevBuf<int32_t> kpre, rps, degs, cols, srcs;
     if (sampled) {
         keep.reset(NW, s);
         kpre.reset(NW + 1, s);
-        degp_buf.reset(n, s);
+        rps.reset(n + 1, s);
+        degs.reset(n, s);
+        cols.reset(E2, s);
+        srcs.reset(E2, s);
         sample_keep_bits(g, salt, thr, keep.get(), kpre.get(), s);
         scan_exclusive_i32(kpre.get(), kpre.get(), NW, s);
-        positions_at_rows(g->row_ptr, n, E2, keep.get(), kpre.get(), nullptr, degp_buf.get(), s);
-        degp = degp_buf.get();
+        positions_at_rows(g->row_ptr, n, E2, keep.get(), kpre.get(), rps.get(), degs.get(), s);
+        compact_kept(g->col, g->src, E2, keep.get(), kpre.get(), cols.get(), srcs.get(), s);
+        v_row = rps.get();
+        v_col = cols.get();
+        v_src = srcs.get();
+        degp = degs.get();
+        E2_dev = kpre.get() + NW;  // 2 m'
     }
 
     // 2. orientation by (deg, id): compacted up lists N+(x) and down lists N-(x)
     DevBuf<uint64_t> ubits(NW, s), dbits(NW, s);
     DevBuf<int32_t> upre(NW + 1, s), dpre(NW + 1, s);
-    TC_LAUNCH("orient_bits", k_orient_bits, dim3(grid_for(E2, 256)), dim3(256), 0, s, g->src, g->col, E2,
-              (const uint64_t*)keep.get(), degp, ubits.get(), upre.get(), dbits.get(), dpre.get());
+    TC_LAUNCH("orient_bits", k_orient_bits, dim3(grid_for(E2, 256)), dim3(256), 0, s, v_src, v_col, E2, E2_dev,
+              (const uint64_t*)nullptr, degp, ubits.get(), upre.get(), dbits.get(), dpre.get());
     scan_exclusive_i32(upre.get(), upre.get(), NW, s);
     scan_exclusive_i32(dpre.get(), dpre.get(), NW, s);
     const int32_t* mp_dev = upre.get() + NW;  // number of up entries = m'
     DevBuf<int32_t> rpO(n + 1, s), dplus(n, s), rpD(n + 1, s), dminus(n, s);
-    positions_at_rows(g->row_ptr, n, E2, ubits.get(), upre.get(), rpO.get(), dplus.get(), s);
-    positions_at_rows(g->row_ptr, n, E2, dbits.get(), dpre.get(), rpD.get(), dminus.get(), s);
+    positions_at_rows(v_row, n, E2, ubits.get(), upre.get(), rpO.get(), dplus.get(), s);
+    positions_at_rows(v_row, n, E2, dbits.get(), dpre.get(), rpD.get(), dminus.get(), s);
     // m' <= m: size the lists by m
     DevBuf<int32_t> colO(g->m, s), srcO(g->m, s), colD(g->m, s), srcD(g->m, s);
-    compact_kept(g->col, g->src, E2, ubits.get(), upre.get(), colO.get(), srcO.get(), s);
-    compact_kept(g->col, g->src, E2, dbits.get(), dpre.get(), colD.get(), srcD.get(), s);
+    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), srcO.get(), s);
+    compact_kept(v_col, v_src, E2, dbits.get(), dpre.get(), colD.get(), srcD.get(), s);
 
     // 3. classification, anchor work, item lists
     const int32_t vcap = cfg.vmajor_cap;
