@@ -123,6 +123,77 @@ def batched(args):
           flush=True)
 
 
+def serve(args):
+    """Serving: ``--requests`` R-MAT requests (scale uniform in [10, 20], edge
+    factor 16, generator seed 1000 + i) counted at p uniform in {1, .5, .1}
+    (sample seed i) by the serving engine with an 8 GiB arena.  Poisson
+    arrivals (seed 12345) at 0.5, 0.8 and 0.95 x the measured one-at-a-time
+    capacity; 4 lanes against 1 lane (one request at a time, arrival order) on
+    the same trace.  Latency = result ready - arrival; every request's counts
+    must be identical in every run."""
+    import concurrent.futures as cf
+    import numpy as np
+    import synth
+    import paper_1011_0468_amd as tc
+
+    N = args.requests
+    scales, ps = synth.serving_requests(N)
+    reqs = [None] * N
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:  # the generator releases the GIL
+        futs = {ex.submit(synth.serving_graph, i, scales[i]): i for i in range(N)}
+        for k, f in enumerate(cf.as_completed(futs)):
+            reqs[futs[f]] = f.result()
+            if (k + 1) % 200 == 0:
+                print("generated %d/%d requests (%.1f s)" % (k + 1, N, time.perf_counter() - t),
+                      file=sys.stderr, flush=True)
+    pairs = int(sum(len(r[1]) for r in reqs))
+    budget = 8 << 30
+
+    def run(lanes, arrivals):
+        with tc.Server(budget, lanes=lanes) as sv:
+            t0 = sv.clock() + 0.05
+            for i, (n, s, d) in enumerate(reqs):
+                sv.submit(i, float(ps[i]), i, arrival_s=t0 + (arrivals[i] if arrivals is not None else 0.0),
+                          n=n, src=s, dst=d)
+            res = sv.drain()
+            st = sv.stats()
+        assert len(res) == N and all(x["status"] == 0 for x in res), [x["message"] for x in res if x["status"]][:3]
+        assert st["spilled_bytes"] == 0
+        res.sort(key=lambda x: x["id"])
+        lat = np.array([x["done_s"] - x["arrival_s"] for x in res]) * 1e3
+        span = max(x["done_s"] for x in res) - min(x["arrival_s"] for x in res)
+        edges = sum(x["counts"]["m"] for x in res)
+        out = {"lanes": lanes, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3), "req_per_s": round(N / span, 2),
+               "edges_per_s": edges / span, "span_s": round(span, 3), "arena_peak": st["arena_peak"]}
+        print("lanes %d: %s" % (lanes, json.dumps(out)), file=sys.stderr, flush=True)
+        return out, [x["counts"] for x in res]
+
+    closed1, ref = run(1, None)
+    closed4, c4 = run(4, None)
+    assert c4 == ref
+    mu1 = closed1["req_per_s"]
+    loads = {}
+    for f in (0.5, 0.8, 0.95):
+        arr = synth.poisson_arrivals(N, f * mu1, 12345)
+        r4, c = run(4, arr)
+        assert c == ref
+        r1, c = run(1, arr)
+        assert c == ref
+        loads[str(f)] = {"lambda_req_per_s": round(f * mu1, 2), "lanes4": r4, "fifo": r1}
+    head = loads["0.8"]
+    print(json.dumps({"metric": "serving p99 latency at 0.8 x one-at-a-time capacity", "value": head["lanes4"]["p99_ms"],
+                      "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "int32", "data": "synthetic",
+                      "fifo_p99_ms": head["fifo"]["p99_ms"], "capacity_req_per_s": {"fifo": mu1,
+                                                                                  "lanes4": closed4["req_per_s"]},
+                      "closed_loop": {"fifo": closed1, "lanes4": closed4}, "loads": loads,
+                      "identical_alone_and_in_mix": True,
+                      "config": {"workload": "serve", "requests": N, "pairs": pairs, "scales": [10, 20],
+                                 "ps": list(synth.SERVE_P), "budget_bytes": budget, "arrival_seed": 12345}}),
+          flush=True)
+
+
 def copy_probe(mib):
     """A plain device copy of known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -144,6 +215,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0)
+    ap.add_argument("--requests", type=int, default=1000, help="serving workload: number of requests")
     ap.add_argument("--autotune", action="store_true",
                     help="search launch parameters per operating point before timing (default: library defaults)")
     args = ap.parse_args()
@@ -161,6 +233,9 @@ def main():
 
     if args.workload == "cl20":
         batched(args)
+        return
+    if args.workload == "serve":
+        serve(args)
         return
 
     import synth

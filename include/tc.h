@@ -171,6 +171,83 @@ void tc_graph_free(tc_graph g);
 /* Message of the last failed call on this thread ("" if none). */
 const char* tc_last_error(void);
 
+/* ---- serving ------------------------------------------------------------- */
+
+/* A server answers independent estimate requests (the sparsify-then-count
+   estimate of section 3.1 for one seed, or the exact count for p = 1) with a
+   fixed device memory arena and a fixed number of concurrent lanes.
+
+   - Admission: a request needs tc_request_bytes() of the arena, the sum of the
+     sizes of every device allocation its CSR build and count make.  Requests
+     are released at their arrival time and admitted strictly in submission
+     order, each as soon as a contiguous range of that size is free.  A request
+     that needs more than the whole budget is rejected at submission
+     (TC_ERR_BUDGET).  The arena is allocated once, at creation, through the
+     installed allocator; nothing is allocated from the device while serving.
+   - Lanes: each lane is a host worker thread with its own stream (default
+     priority).  lanes = 1 serves one request at a time in arrival order.
+   - Results equal those of tc_build_csr + tc_estimate with the same (p, seed)
+     and default tc_params, bit for bit, whatever else is in flight.
+   - Thread safety: every tc_server_* call may come from any thread. */
+typedef struct tc_server_s* tc_server;
+
+typedef struct {
+    int64_t budget_bytes;  /* device arena size (rounded down to 256 B); 0 admits nothing */
+    int32_t lanes;         /* concurrent requests, 1..16 */
+    int32_t reserved;      /* must be 0 */
+} tc_server_config;
+
+typedef struct {
+    uint64_t id;            /* caller's tag, copied to the result */
+    tc_graph graph;         /* resident graph to count, or NULL to build one from the pairs below;
+                               borrowed until the request's result has been polled */
+    int64_t n;              /* pairs input: vertex count and pairs in host memory, borrowed until */
+    int64_t num_pairs;      /*   the result has been polled (the same rules as tc_build_csr) */
+    const int32_t* src;
+    const int32_t* dst;
+    double p;               /* keep probability in (0, 1]; 1 counts exactly */
+    uint64_t seed;          /* sampling seed (unused for p = 1) */
+    double arrival_s;       /* release time on the server clock (tc_server_clock); earlier = now */
+} tc_request;
+
+typedef struct {
+    uint64_t id;
+    int32_t status;          /* tc_status of this request */
+    int32_t lane;            /* lane that ran it */
+    tc_counts counts;        /* as tc_estimate's per_seed entry */
+    double estimate;         /* counts.triangles / ((p*p)*p) */
+    double arrival_s;        /* release time: max(arrival_s, time of submission) */
+    double start_s;          /* admission time */
+    double done_s;           /* result ready; latency = done_s - arrival_s */
+    int64_t reserved_bytes;  /* arena bytes reserved at admission (tc_request_bytes) */
+    int64_t peak_bytes;      /* high-water mark of its allocations inside the reservation */
+    int64_t spilled_bytes;   /* allocations that did not fit and went to the installed allocator (0 expected) */
+    char message[96];        /* error text when status != TC_OK */
+} tc_result;
+
+typedef struct {
+    int64_t submitted, completed, rejected, queued, running;
+    int64_t arena_bytes, arena_used, arena_peak, spilled_bytes;
+} tc_server_info;
+
+/* Arena bytes a request needs; no device work.  TC_ERR_INVALID / OVERFLOW for
+   requests tc_server_submit would refuse. */
+tc_status tc_request_bytes(const tc_request* r, int64_t* bytes);
+/* New server; its clock starts at 0.  TC_ERR_OOM if the arena cannot be allocated. */
+tc_status tc_server_create(const tc_server_config* cfg, tc_server* out);
+/* Seconds on the server clock. */
+tc_status tc_server_clock(tc_server s, double* now_s);
+/* Queue a copy of *r (the arrays it points to stay borrowed).  Does not block. */
+tc_status tc_server_submit(tc_server s, const tc_request* r);
+/* Move up to cap finished results into out[], in completion order.  Waits up
+   to timeout_s seconds (< 0: no limit) until at least one result is ready or
+   nothing is queued or running; *got receives the number written. */
+tc_status tc_server_poll(tc_server s, tc_result* out, int32_t cap, double timeout_s, int32_t* got);
+tc_status tc_server_stats(tc_server s, tc_server_info* out);
+/* Wait for every submitted request, then release the server (NULL is
+   ignored).  Results not yet polled are discarded. */
+void tc_server_destroy(tc_server s);
+
 /* ---- measurement hooks --------------------------------------------------- */
 
 /* When enabled, every kernel launch is bracketed by HIP events on its stream

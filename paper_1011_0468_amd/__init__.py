@@ -15,10 +15,11 @@ import ctypes
 import numpy as np
 
 from . import _native
-from ._native import TcCounts, TcError, TcParams, TcTuning, check
+from ._native import TcCounts, TcError, TcParams, TcRequest, TcResult, TcServerConfig, TcServerInfo, TcTuning, check
 
 __all__ = ["Graph", "tc_build_csr", "tc_sample", "tc_count_exact", "tc_estimate", "tc_rp_trace",
-           "tc_graph_info", "tc_graph_read", "tc_tune_set", "tc_tune_get", "tc_autotune", "profile", "TcError"]
+           "tc_graph_info", "tc_graph_read", "tc_tune_set", "tc_tune_get", "tc_autotune", "profile", "TcError",
+           "Server", "tc_request_bytes"]
 
 
 def _stream_ptr(stream):
@@ -182,3 +183,110 @@ class profile:
         ms, cnt = ctypes.c_double(0.0), ctypes.c_int64(0)
         check(_native.load().tc_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
+
+
+def _request(req_id, p, seed, arrival_s=0.0, graph=None, n=0, src=None, dst=None):
+    r = TcRequest()
+    r.id = int(req_id) & (2 ** 64 - 1)
+    r.p = float(p)
+    r.seed = int(seed) & (2 ** 64 - 1)
+    r.arrival_s = float(arrival_s)
+    if graph is not None:
+        r.graph = graph.handle
+    else:
+        r.n = int(n)
+        r.num_pairs = int(len(src))
+        r.src = src.ctypes.data if len(src) else None
+        r.dst = dst.ctypes.data if len(dst) else None
+    return r
+
+
+def _host_pairs(src, dst):
+    src = np.ascontiguousarray(np.asarray(src), dtype=np.int32)
+    dst = np.ascontiguousarray(np.asarray(dst), dtype=np.int32)
+    if src.shape != dst.shape or src.ndim != 1:
+        raise ValueError("src and dst must be 1-D arrays of equal length")
+    return src, dst
+
+
+def tc_request_bytes(p, graph=None, n=0, src=None, dst=None):
+    """Arena bytes a serving request needs (no device work)."""
+    if graph is None:
+        src, dst = _host_pairs(src, dst)
+    r = _request(0, p, 0, 0.0, graph, n, src, dst)
+    out = ctypes.c_int64(0)
+    check(_native.load().tc_request_bytes(ctypes.byref(r), ctypes.byref(out)))
+    return out.value
+
+
+class Server:
+    """Serving engine (``tc_server_*``): a device arena of ``budget_bytes`` and
+    ``lanes`` concurrent requests.  Host arrays and graphs of submitted
+    requests are kept referenced here until their results are polled."""
+
+    def __init__(self, budget_bytes, lanes=4):
+        cfg = TcServerConfig(int(budget_bytes), int(lanes), 0)
+        h = ctypes.c_void_p(0)
+        check(_native.load().tc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._held = {}
+
+    def clock(self):
+        t = ctypes.c_double(0.0)
+        check(_native.load().tc_server_clock(self._h, ctypes.byref(t)))
+        return t.value
+
+    def submit(self, req_id, p, seed, arrival_s=0.0, graph=None, n=0, src=None, dst=None):
+        """Queue a request: a resident ``graph``, or host pairs (``n``, ``src``, ``dst``)."""
+        if graph is None:
+            src, dst = _host_pairs(src, dst)
+        if req_id in self._held:
+            raise ValueError("request id %r is already in flight" % (req_id,))
+        r = _request(req_id, p, seed, arrival_s, graph, n, src, dst)
+        check(_native.load().tc_server_submit(self._h, ctypes.byref(r)))
+        self._held[req_id] = (graph, src, dst)
+
+    def poll(self, cap=64, timeout_s=-1.0):
+        """Finished results (dicts), waiting up to ``timeout_s`` for the first."""
+        buf = (TcResult * max(1, int(cap)))()
+        got = ctypes.c_int32(0)
+        check(_native.load().tc_server_poll(self._h, buf, int(cap), float(timeout_s), ctypes.byref(got)))
+        out = []
+        for i in range(got.value):
+            d = buf[i].as_dict()
+            self._held.pop(d["id"], None)
+            out.append(d)
+        return out
+
+    def drain(self):
+        """Every outstanding result."""
+        out = []
+        while self._held:
+            part = self.poll(256, -1.0)
+            if not part:
+                break
+            out.extend(part)
+        return out
+
+    def stats(self):
+        st = TcServerInfo()
+        check(_native.load().tc_server_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self._h and self._h.value:
+            _native.load().tc_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+            self._held.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

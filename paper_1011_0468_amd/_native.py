@@ -36,6 +36,38 @@ class TcTuning(ctypes.Structure):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
+class TcServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class TcRequest(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("graph", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("num_pairs", ctypes.c_int64), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("p", ctypes.c_double), ("seed", ctypes.c_uint64), ("arrival_s", ctypes.c_double)]
+
+
+class TcResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("lane", ctypes.c_int32),
+                ("counts", TcCounts), ("estimate", ctypes.c_double), ("arrival_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double), ("reserved_bytes", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("spilled_bytes", ctypes.c_int64), ("message", ctypes.c_char * 96)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name not in ("counts", "message")}
+        d["counts"] = self.counts.as_dict()
+        d["message"] = self.message.decode(errors="replace")
+        return d
+
+
+class TcServerInfo(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("submitted", "completed", "rejected", "queued", "running", "arena_bytes", "arena_used",
+                 "arena_peak", "spilled_bytes")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 class TcError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
@@ -49,6 +81,8 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 EXPORTS = ["tc_set_allocator", "tc_build_csr", "tc_graph_info", "tc_graph_csr", "tc_graph_read", "tc_sample",
            "tc_count_exact", "tc_estimate", "tc_rp_trace", "tc_tune_set", "tc_tune_get", "tc_autotune",
            "tc_graph_free", "tc_last_error",
+           "tc_request_bytes", "tc_server_create", "tc_server_clock", "tc_server_submit", "tc_server_poll",
+           "tc_server_stats", "tc_server_destroy",
            "tc_profile_enable", "tc_profile_select", "tc_profile_reset", "tc_profile_read"]
 
 _lib = None
@@ -77,6 +111,12 @@ def load():
         "tc_tune_set": [vp, dbl, P(TcTuning)],
         "tc_tune_get": [vp, dbl, P(TcTuning)],
         "tc_autotune": [vp, dbl, u64, i32, vp, P(TcTuning)],
+        "tc_request_bytes": [P(TcRequest), P(i64)],
+        "tc_server_create": [P(TcServerConfig), P(vp)],
+        "tc_server_clock": [vp, P(dbl)],
+        "tc_server_submit": [vp, P(TcRequest)],
+        "tc_server_poll": [vp, P(TcResult), i32, dbl, P(i32)],
+        "tc_server_stats": [vp, P(TcServerInfo)],
         "tc_profile_enable": [i32],
         "tc_profile_reset": [],
         "tc_profile_select": [ctypes.c_char_p],
@@ -88,6 +128,8 @@ def load():
         f.restype = ctypes.c_int
     L.tc_graph_free.argtypes = [vp]
     L.tc_graph_free.restype = None
+    L.tc_server_destroy.argtypes = [vp]
+    L.tc_server_destroy.restype = None
     L.tc_last_error.argtypes = []
     L.tc_last_error.restype = ctypes.c_char_p
     _lib = L

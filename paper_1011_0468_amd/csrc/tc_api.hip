@@ -22,6 +22,8 @@ static thread_local std::string g_last_error;
 
 void fail(tc_status st, const std::string& msg) { throw Error{st, msg}; }
 
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
 void check_hip(hipError_t e, const char* what) {
     if (e != hipSuccess) fail(TC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -109,7 +111,19 @@ void pool_free(void* p, hipStream_t s) {
 
 }  // namespace
 
+static thread_local AllocRegion* t_region = nullptr;
+
+AllocRegion* set_thread_region(AllocRegion* r) {
+    AllocRegion* old = t_region;
+    t_region = r;
+    return old;
+}
+
 void* dev_alloc(size_t bytes, hipStream_t s) {
+    if (t_region) {
+        if (void* p = t_region->try_alloc(bytes ? bytes : 1)) return p;
+        t_region->spilled += (int64_t)bytes;
+    }
     tc_alloc_fn a;
     void* ctx;
     {
@@ -124,6 +138,7 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
 
 void dev_free(void* p, hipStream_t s) {
     if (!p) return;
+    if (t_region && t_region->try_free(p)) return;
     tc_free_fn f;
     void* ctx;
     {
@@ -243,7 +258,25 @@ tc_status guarded(F&& f) {
     }
 }
 
+
+}  // namespace
+
+namespace tc {
+
 bool p_valid(double p) { return std::isfinite(p) && p > 0.0 && p <= 1.0; }
+
+int num_cus() {
+    // compute units of the current device (256 on MI355X), read once
+    static const int cus = [] {
+        int dev = 0, c = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            c = prop.multiProcessorCount;
+        (void)hipGetLastError();
+        return c > 0 ? c : 256;
+    }();
+    return cus;
+}
 
 CountConfig config_from(const tc_params* prm, const tc_graph_s* g, int sampled, double p) {
     CountConfig c;
@@ -295,7 +328,36 @@ int32_t max_degree(const tc_graph_s* g, hipStream_t s) {
     return h;
 }
 
-}  // namespace
+tc_graph_s* graph_from_pairs(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst, int on_device,
+                             hipStream_t s) {
+    if (n < 0 || num_pairs < 0) fail(TC_ERR_INVALID, "n and num_pairs must be >= 0");
+    if (num_pairs > 0 && (!src || !dst)) fail(TC_ERR_INVALID, "src/dst is NULL");
+    if (n > 0x7fffffffLL) fail(TC_ERR_OVERFLOW, "n exceeds 2^31-1");
+    if (2 * num_pairs > 0x7fffffffLL) fail(TC_ERR_OVERFLOW, "2*num_pairs exceeds 2^31-1 (int32 CSR)");
+    DevBuf<int32_t> hs, hd;
+    const int32_t* ds = src;
+    const int32_t* dd = dst;
+    if (!on_device && num_pairs > 0) {
+        hs.reset(num_pairs, s);
+        hd.reset(num_pairs, s);
+        check_hip(hipMemcpyAsync(hs.get(), src, sizeof(int32_t) * num_pairs, hipMemcpyHostToDevice, s), "H2D src");
+        check_hip(hipMemcpyAsync(hd.get(), dst, sizeof(int32_t) * num_pairs, hipMemcpyHostToDevice, s), "H2D dst");
+        ds = hs.get();
+        dd = hd.get();
+    }
+    tc_graph_s* g = new tc_graph_s();
+    try {
+        if (build_csr(n, num_pairs, ds, dd, s, g)) fail(TC_ERR_INVALID, "vertex id outside [0, n)");
+        g->max_deg = max_degree(g, s);
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        graph_release(g);
+        throw;
+    }
+    return g;
+}
+
+}  // namespace tc
 
 extern "C" {
 
@@ -313,32 +375,7 @@ tc_status tc_build_csr(int64_t n, int64_t num_pairs, const int32_t* src, const i
                        void* stream, tc_graph* out) {
     return guarded([&] {
         if (!out) fail(TC_ERR_INVALID, "out is NULL");
-        if (n < 0 || num_pairs < 0) fail(TC_ERR_INVALID, "n and num_pairs must be >= 0");
-        if (num_pairs > 0 && (!src || !dst)) fail(TC_ERR_INVALID, "src/dst is NULL");
-        if (n > 0x7fffffffLL) fail(TC_ERR_OVERFLOW, "n exceeds 2^31-1");
-        if (2 * num_pairs > 0x7fffffffLL) fail(TC_ERR_OVERFLOW, "2*num_pairs exceeds 2^31-1 (int32 CSR)");
-        hipStream_t s = (hipStream_t)stream;
-        DevBuf<int32_t> hs, hd;
-        const int32_t* ds = src;
-        const int32_t* dd = dst;
-        if (!on_device && num_pairs > 0) {
-            hs.reset(num_pairs, s);
-            hd.reset(num_pairs, s);
-            check_hip(hipMemcpyAsync(hs.get(), src, sizeof(int32_t) * num_pairs, hipMemcpyHostToDevice, s), "H2D src");
-            check_hip(hipMemcpyAsync(hd.get(), dst, sizeof(int32_t) * num_pairs, hipMemcpyHostToDevice, s), "H2D dst");
-            ds = hs.get();
-            dd = hd.get();
-        }
-        tc_graph_s* g = new tc_graph_s();
-        try {
-            if (build_csr(n, num_pairs, ds, dd, s, g)) fail(TC_ERR_INVALID, "vertex id outside [0, n)");
-            g->max_deg = max_degree(g, s);
-        } catch (...) {
-            check_hip(hipStreamSynchronize(s), "sync");
-            graph_release(g);
-            throw;
-        }
-        *out = g;
+        *out = graph_from_pairs(n, num_pairs, src, dst, on_device, (hipStream_t)stream);
     });
 }
 

@@ -41,18 +41,6 @@ unsigned grid_for(int64_t N, int threads) {
     return b ? b : 1;
 }
 
-int num_cus() {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-        if (cus <= 0) cus = 256;
-    }
-    return cus;
-}
-
 // Entries of an iterated list processed by one work item.
 constexpr int kJL = 256;
 // Largest anchor out-degree whose table the block kernel keeps in LDS.
@@ -764,11 +752,42 @@ __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ 
 
 // Heavy-vertex bound: heavy vertices have deg > c m'^(1/2) with c = a/b and the
 // degrees sum to 2m', so h < 2 m'^(1/2) / c <= 2 b m^(1/2) / a (all n if a = 0).
-static int64_t heavy_bound(const tc_graph_s* g, int32_t a, int32_t b) {
-    if (a == 0) return g->n;
-    const double hb = 2.0 * (double)b * std::sqrt((double)g->m) / (double)a + 2.0;
-    return hb < (double)g->n ? (int64_t)hb : g->n;
+static int64_t heavy_bound(int64_t n, int64_t m, int32_t a, int32_t b) {
+    if (a == 0) return n;
+    const double hb = 2.0 * (double)b * std::sqrt((double)m) / (double)a + 2.0;
+    return hb < (double)n ? (int64_t)hb : n;
 }
+
+// Which block-per-item bins a count launches, and the table capacity of each
+// (0: not launched).  maxd bounds the out-degree of every anchor.
+struct LightPlan {
+    int32_t dcap_lds = 0;     // anchors with small_dmax < d+ <= kLdsDcap: table in LDS
+    int32_t dcap_global = 0;  // anchors with d+ > kLdsDcap: table in global scratch
+};
+
+static LightPlan light_plan(int64_t m, int32_t maxd, const CountConfig& cfg) {
+    LightPlan pl;
+    if (maxd > cfg.small_dmax) {
+        int32_t dcap = 64;
+        while (dcap < std::min<int32_t>(maxd, kLdsDcap)) dcap <<= 1;
+        pl.dcap_lds = dcap;
+    }
+    if (maxd > kLdsDcap) {
+        // anchors of this bin: light sources (d+ <= deg <= c m'^(1/2) <= c m^(1/2)) or
+        // v-side anchors (d+ <= vmajor_cap)
+        const double light_cap = cfg.heavy_num == 0 ? 0.0
+                                 : (double)cfg.heavy_num * std::sqrt((double)m) / (double)cfg.heavy_den + 1.0;
+        int64_t dbound = std::max<int64_t>((int64_t)cfg.vmajor_cap, (int64_t)std::min(light_cap, (double)maxd));
+        dbound = std::min<int64_t>(dbound, maxd);
+        int32_t dcap = 64;
+        while (dcap < dbound) dcap <<= 1;
+        if (dbound > kLdsDcap) pl.dcap_global = dcap;
+    }
+    return pl;
+}
+
+// int32 words of one block's table, list staging and marks
+static int64_t large_block_words(int32_t dcap) { return (4 * (int64_t)dcap + 2 * kJL + 1 + 256 * kU + 3) / 4 * 4; }
 
 void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
                    hipStream_t s, int64_t* acc) {
@@ -780,7 +799,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     const int64_t NW = (E2 + 63) / 64;
 
     // host-side bounds for every launch (no read-back inside a count)
-    const int64_t hmax = heavy_bound(g, cfg.heavy_num, cfg.heavy_den);
+    const int64_t hmax = heavy_bound(n, g->m, cfg.heavy_num, cfg.heavy_den);
     const int64_t hp_max = (hmax + 31) / 32 * 32;
     if (hp_max * hp_max > ((int64_t)16 << 30))
         fail(TC_ERR_OVERFLOW, "heavy block bound exceeds 16 GiB: raise the heavy threshold");
@@ -876,7 +895,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
                   (const int32_t*)base.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
                   (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
         // tab: 4 * next_pow2(d) <= 4 * dcap slots, P: kJL+1, S: kJL, marks: 4*64*kU (16-byte multiple)
-        const size_t per_block = (size_t)((4 * dcap + 2 * kJL + 1 + 256 * kU + 3) / 4 * 4);
+        const size_t per_block = (size_t)large_block_words(dcap);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
         if (!global) {
             // resident blocks per CU: 160 KB of LDS per CU on gfx950, at most 8 blocks of 4 waves
@@ -897,22 +916,9 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
                       (const int2*)packD.get(), dcap, gscr.get(), acc);
         }
     };
-    if (maxd > cfg.small_dmax) {
-        int32_t dcap = 64;
-        while (dcap < std::min<int32_t>(maxd, kLdsDcap)) dcap <<= 1;
-        launch_large(nlg, lbase, dcap, false);
-    }
-    if (maxd > kLdsDcap) {
-        // anchors of this bin: light sources (d+ <= deg <= c m'^(1/2) <= c m^(1/2)) or
-        // v-side anchors (d+ <= vmajor_cap)
-        const double light_cap = cfg.heavy_num == 0 ? 0.0
-                                 : (double)cfg.heavy_num * std::sqrt((double)g->m) / (double)cfg.heavy_den + 1.0;
-        int64_t dbound = std::max<int64_t>((int64_t)vcap, (int64_t)std::min(light_cap, (double)maxd));
-        dbound = std::min<int64_t>(dbound, maxd);
-        int32_t dcap = 64;
-        while (dcap < dbound) dcap <<= 1;
-        if (dbound > kLdsDcap) launch_large(nhg, hbase, dcap, true);
-    }
+    const LightPlan plan = light_plan(g->m, maxd, cfg);
+    if (plan.dcap_lds) launch_large(nlg, lbase, plan.dcap_lds, false);
+    if (plan.dcap_global) launch_large(nhg, hbase, plan.dcap_global, true);
 
     // 5. heavy phase: sized by the bound, trimmed to the device's h inside the kernels
     if (hmax >= 3) {
@@ -950,6 +956,33 @@ void counts_from_slots(const int64_t* hacc, tc_counts* out) {
     res.model_bytes_small = hacc[kBytesSmall];
     res.model_bytes_large = hacc[kBytesLarge];
     *out = res;
+}
+
+int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const CountConfig& cfg) {
+    auto rb = region_bytes;
+    int64_t b = rb(8 * kCountSlots);  // acc of count_core
+    const int64_t E2 = 2 * m;
+    if (n == 0 || E2 == 0) return b;
+    const int64_t NW = (E2 + 63) / 64;
+    if (sampled)
+        b += rb(8 * NW) + rb(4 * (NW + 1)) + rb(4 * (n + 1)) + rb(4 * n) + 2 * rb(4 * E2) + scan_scratch_bytes(NW);
+    b += 2 * rb(8 * NW) + 2 * rb(4 * (NW + 1)) + 2 * scan_scratch_bytes(NW);  // orientation bits, prefixes
+    b += 2 * rb(4 * (n + 1)) + 2 * rb(4 * n);                                 // rpO, d+, rpD, d-
+    b += 4 * rb(4 * m);                                                        // up and down lists
+    b += rb(4 * (n + 1)) + rb(4 * n) + 2 * rb(8 * n);                          // heavy, code, Wu, Wv
+    b += rb(8 * m) + rb(8 * (cfg.vmajor_cap > 0 ? m : 1));                     // packed descriptors
+    b += 7 * rb(4 * (n + 1)) + 4 * scan_scratch_bytes(n);                      // item counts and bases
+    const int64_t items_max = 2 * n + E2 / kJL + 2;
+    b += rb(8 * items_max);
+    const LightPlan plan = light_plan(m, maxd, cfg);
+    if (plan.dcap_lds) b += rb(8 * items_max);
+    if (plan.dcap_global) b += rb(8 * items_max) + rb(4 * (int64_t)num_cus() * large_block_words(plan.dcap_global));
+    const int64_t hmax = heavy_bound(n, m, cfg.heavy_num, cfg.heavy_den);
+    if (hmax >= 3) {
+        const int64_t hp = (hmax + 31) / 32 * 32;
+        b += 2 * rb(4 * hmax) + rb(4 * n) + 2 * rb(hp * hp);
+    }
+    return b;
 }
 
 void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,

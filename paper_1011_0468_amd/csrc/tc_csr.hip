@@ -202,9 +202,29 @@ int build_csr_t(int64_t n, int64_t P, const int32_t* src, const int32_t* dst, in
 
 }  // namespace
 
-int build_csr(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst, hipStream_t s, tc_graph_s* g) {
+static int key_bits_half(int64_t n) {
     int nb = 1;
     while (nb < 31 && ((int64_t)1 << nb) < n) ++nb;
+    return nb;
+}
+
+int64_t build_csr_bytes(int64_t n, int64_t num_pairs) {
+    auto rb = region_bytes;
+    const int nb = key_bits_half(n);
+    const int64_t K = 2 * nb <= 32 ? 4 : 8;
+    const int64_t N = 2 * num_pairs;
+    int64_t b = 2 * rb(K * N) + rb(4);  // key ping-pong, flag
+    if (N > 0) {
+        const int64_t nblk = (N + kRsTile - 1) / kRsTile;
+        b += rb(4 * (kRadix * nblk + 1)) + scan_scratch_bytes(kRadix * nblk);
+    }
+    b += rb(4 * (N + 1)) + scan_scratch_bytes(N);                              // unique positions
+    b += rb(4 * (n + 1)) + 2 * rb(4 * N) + rb(4 * n) + scan_scratch_bytes(n);  // the CSR (2m <= N)
+    return b;
+}
+
+int build_csr(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst, hipStream_t s, tc_graph_s* g) {
+    const int nb = key_bits_half(n);
     if (2 * nb <= 32) return build_csr_t<uint32_t>(n, num_pairs, src, dst, nb, s, g);
     return build_csr_t<uint64_t>(n, num_pairs, src, dst, nb, s, g);
 }

@@ -26,10 +26,28 @@ struct Error {
 // Thrown inside the library only; every extern "C" entry point catches it.
 [[noreturn]] void fail(tc_status st, const std::string& msg);
 void check_hip(hipError_t e, const char* what);
+// Text returned by tc_last_error() on the calling thread.
+void set_last_error(const std::string& msg);
+
+// A sub-allocator that the calling thread's device allocations go to first
+// (a serving request's reservation).  try_alloc returns nullptr when full, and
+// the allocation then falls back to the installed allocator (counted in
+// spilled); try_free returns false for pointers it does not own.
+struct AllocRegion {
+    int64_t spilled = 0;
+    virtual void* try_alloc(size_t bytes) = 0;
+    virtual bool try_free(void* p) = 0;
+    virtual ~AllocRegion() = default;
+};
+// Install r for the calling thread (nullptr: none); returns the previous one.
+AllocRegion* set_thread_region(AllocRegion* r);
 
 // Device allocation through the installed allocator (throws TC_ERR_OOM).
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
+
+// Bytes a single allocation of b bytes takes in a reservation (256-byte granules).
+inline int64_t region_bytes(int64_t b) { return ((b > 0 ? b : 1) + 255) / 256 * 256; }
 
 // RAII device buffer.
 template <typename T>
@@ -110,6 +128,8 @@ namespace tc {
 
 // Exclusive scan of in[0..N) into out[0..N], out[N] = total.  In-place allowed.
 void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t N, hipStream_t s);
+// Bytes the scratch of one scan of N elements takes (sum of its allocations).
+int64_t scan_scratch_bytes(int64_t N);
 void fill_i32(int32_t* p, int32_t v, int64_t N, hipStream_t s);
 void fill_i64(int64_t* p, int64_t v, int64_t N, hipStream_t s);
 void fill_u8(uint8_t* p, uint8_t v, int64_t N, hipStream_t s);
@@ -121,6 +141,8 @@ void fill_u8(uint8_t* p, uint8_t v, int64_t N, hipStream_t s);
 // Build into g (allocations through dev_alloc).  Returns 0 or 1 if an id is out of range.
 int build_csr(int64_t n, int64_t num_pairs, const int32_t* src_dev, const int32_t* dst_dev,
               hipStream_t s, tc_graph_s* g);
+// Sum of the sizes of every allocation build_csr makes (region_bytes each).
+int64_t build_csr_bytes(int64_t n, int64_t num_pairs);
 
 // ---------------------------------------------------------------------------
 // Sampling (tc_sample.hip)
@@ -159,6 +181,9 @@ constexpr int kCountSlots = 16;
 void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
                    hipStream_t s, int64_t* acc);
 void counts_from_slots(const int64_t* hacc, tc_counts* out);
+// Sum of the sizes of every allocation count_core makes (region_bytes each) on
+// a graph of n vertices, m edges and maximum degree maxd.
+int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const CountConfig& cfg);
 // count_enqueue + read-back (synchronises s).
 void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
                 hipStream_t s, tc_counts* out);
@@ -168,6 +193,20 @@ void count_core(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, c
 // ---------------------------------------------------------------------------
 
 void rp_trace(const tc_graph_s* g, int32_t k, uint64_t seed, hipStream_t s, int64_t* q_host);
+
+// ---------------------------------------------------------------------------
+// Host helpers of the entry points (tc_api.hip)
+// ---------------------------------------------------------------------------
+
+bool p_valid(double p);
+CountConfig config_from(const tc_params* prm, const tc_graph_s* g, int sampled, double p);
+double rescale(int64_t T, double p);
+int32_t max_degree(const tc_graph_s* g, hipStream_t s);
+void graph_release(tc_graph_s* g);
+// CSR of the pairs (host arrays copied in unless on_device); throws on error.
+tc_graph_s* graph_from_pairs(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst, int on_device,
+                             hipStream_t s);
+int num_cus();
 
 // Autotuned parameters for a graph signature (tc_tune.hip)
 CountConfig tuned_config(const tc_graph_s* g, int sampled, double p, const CountConfig& base);

@@ -98,6 +98,12 @@ void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t N, hipStream_t 
               (const int32_t*)bs.get());
 }
 
+int64_t scan_scratch_bytes(int64_t N) {
+    if (N <= kScanTile) return 0;
+    const int64_t nb = (N + kScanTile - 1) / kScanTile;
+    return region_bytes(4 * (nb + 1)) + scan_scratch_bytes(nb);
+}
+
 void fill_i32(int32_t* p, int32_t v, int64_t N, hipStream_t s) { fill_impl<int32_t>(p, v, N, s); }
 void fill_i64(int64_t* p, int64_t v, int64_t N, hipStream_t s) { fill_impl<int64_t>(p, v, N, s); }
 void fill_u8(uint8_t* p, uint8_t v, int64_t N, hipStream_t s) { fill_impl<uint8_t>(p, v, N, s); }

@@ -132,6 +132,24 @@ def uniform_ints(count, bound, seed, stream=0x494e5453):
 _CACHE = {}
 
 
+SERVE_P = (1.0, 0.5, 0.1)
+
+
+def serving_requests(count, scale_lo=10, scale_hi=20, seed=12345):
+    """Request mix of the serving workload: request i is an R-MAT graph of
+    scale ``scale[i]`` uniform in [scale_lo, scale_hi] (edge factor 16,
+    generator seed 1000 + i) counted at p uniform in {1, .5, .1} with sample
+    seed i.  Returns (scales int32[count], p float64[count])."""
+    scales = uniform_ints(count, scale_hi - scale_lo + 1, seed, stream=0x5343414C) + scale_lo
+    pidx = uniform_ints(count, len(SERVE_P), seed, stream=0x50524F42)
+    return scales.astype(np.int32), np.array([SERVE_P[k] for k in pidx], dtype=np.float64)
+
+
+def serving_graph(i, scale):
+    """Pairs of serving request i (R-MAT, edge factor 16, seed 1000 + i)."""
+    return rmat(int(scale), 16, seed=1000 + int(i))
+
+
 def workload(name):
     """Named synthetic workloads, cached per process.
 
