@@ -194,6 +194,73 @@ def serve(args):
           flush=True)
 
 
+def top_degree_subgraph(n, src, dst, deg, h):
+    """Pairs of the subgraph induced by the h vertices of largest (degree, id),
+    relabelled 0..h-1 in that order."""
+    import numpy as np
+    order = np.lexsort((np.arange(n), deg))[::-1][:h]
+    lab = np.full(n, -1, np.int64)
+    lab[order] = np.arange(h)
+    keep = (lab[src] >= 0) & (lab[dst] >= 0)
+    return lab[src[keep]].astype(np.int32), lab[dst[keep]].astype(np.int32)
+
+
+def heavy_stress(args):
+    """MFMA stress shape: the subgraph induced by the h highest-degree vertices
+    of R-MAT s24 (h = 4096, 8192, 16384), counted with every vertex heavy
+    (heavy_num = 0), so the whole count runs through the int8-MFMA block; the
+    count is checked against the light/heavy split count of the same graph.
+    Ops: the oriented form does one multiply-add per triple i < k < j,
+    h^3/3 ops; the kernel executes 2 * 128^2 * 128 (J - I + 1) ops per macro
+    tile I <= J."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1011_0468_amd as tc
+    n, s, d = synth.workload("rmat24")
+    g = tc.tc_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    _, _, deg = g.read()
+    g.free()
+    torch.cuda.empty_cache()
+    rows = []
+    for h in (4096, 8192, 16384):
+        hs, hd = top_degree_subgraph(n, s, d, deg.astype(np.int64), h)
+        sg = tc.tc_build_csr(h, torch.from_numpy(hs).cuda(), torch.from_numpy(hd).cuda())
+        m = sg.info()["m"]
+        ref = tc.tc_count_exact(sg)
+        c = tc.tc_count_exact(sg, heavy=(0, 1))
+        assert c["triangles"] == ref["triangles"] and c["light"] == 0
+        tc.profile.select(["heavy_mfma"])
+        tc.profile.reset()
+        tc.profile.enable(True)
+        for _ in range(args.steps):
+            tc.tc_count_exact(sg, heavy=(0, 1))
+        torch.cuda.synchronize()
+        tc.profile.enable(False)
+        ms_tot, launches = tc.profile.read("heavy_mfma")
+        ms = ms_tot / launches
+        hh = c["n_heavy"]
+        nm = (hh + 127) // 128
+        executed = 2 * 128 ** 3 * sum(J - I + 1 for J in range(nm) for I in range(J + 1))
+        oriented = hh ** 3 / 3.0
+        row = {"h": h, "n_heavy": hh, "m": m, "triangles": c["triangles"], "mfma_ms": round(ms, 4),
+               "tops_oriented": round(oriented / (ms / 1e3) / 1e12, 1),
+               "tops_executed": round(executed / (ms / 1e3) / 1e12, 1)}
+        row["frac_executed"] = round(row["tops_executed"] / 5000.0, 4)
+        print("heavy h=%d: %s" % (h, json.dumps(row)), file=sys.stderr, flush=True)
+        rows.append(row)
+        sg.free()
+    top = rows[-1]
+    print(json.dumps({"metric": "int8-MFMA heavy block throughput (top-16384 of R-MAT s24, all heavy)",
+                      "value": top["tops_executed"], "unit": "TOP/s", "n_gpus": 1, "steps": args.steps,
+                      "higher_is_better": True, "dtype": "i8", "data": "synthetic",
+                      "roofline": {"bound": "mfma", "achieved": top["tops_executed"], "peak": 5000.0,
+                                   "unit": "TFLOP/s", "frac": top["frac_executed"], "traffic": None,
+                                   "kernel": "heavy_mfma"},
+                      "shapes": rows, "config": {"workload": "heavy_stress", "graph": "rmat24", "h": [4096, 8192, 16384]}}),
+          flush=True)
+
+
 def copy_probe(mib):
     """A plain device copy of known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -236,6 +303,9 @@ def main():
         return
     if args.workload == "serve":
         serve(args)
+        return
+    if args.workload == "heavy":
+        heavy_stress(args)
         return
 
     import synth

@@ -88,6 +88,10 @@ __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__
     }
 }
 
+// Heavy block: U is stored padded to a multiple of the MFMA macro tile edge.
+constexpr int kHT = 128;
+__host__ __device__ inline int64_t heavy_pad(int64_t h) { return (h + kHT - 1) / kHT * kHT; }
+
 // ---------------------------------------------------------------------------
 // classification and light work
 // ---------------------------------------------------------------------------
@@ -279,10 +283,10 @@ __global__ void k_heavy_list(int64_t n, const int32_t* __restrict__ heavy, const
         if (heavy[x]) hlist[hpos[x]] = (int32_t)x;
 }
 
-// zero the first round32(h)^2 bytes of U and UT (h from device)
+// zero the first heavy_pad(h)^2 bytes of U and UT (h from device)
 __global__ void k_heavy_zero(const int32_t* __restrict__ h_dev, uint8_t* __restrict__ U, uint8_t* __restrict__ UT) {
-    const int64_t hp = ((int64_t)h_dev[0] + 31) / 32 * 32;
-    const int64_t nw = hp * hp / 16;  // 16-byte words (hp is a multiple of 32)
+    const int64_t hp = heavy_pad(h_dev[0]);
+    const int64_t nw = hp * hp / 16;  // 16-byte words (hp is a multiple of 128)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (int64_t)gridDim.x * blockDim.x) {
         reinterpret_cast<int4*>(U)[i] = make_int4(0, 0, 0, 0);
         reinterpret_cast<int4*>(UT)[i] = make_int4(0, 0, 0, 0);
@@ -692,7 +696,7 @@ __global__ void __launch_bounds__(256) k_heavy_pack(const int32_t* __restrict__ 
                                                      const int32_t* __restrict__ hidx, uint8_t* __restrict__ U,
                                                      uint8_t* __restrict__ UT) {
     const int32_t h = h_dev[0];
-    const int32_t hp = (h + 31) / 32 * 32;
+    const int64_t hp = heavy_pad(h);
     const int i = blockIdx.x;
     if (i >= h) return;
     const int32_t x = horder[i];
@@ -706,46 +710,97 @@ __global__ void __launch_bounds__(256) k_heavy_pack(const int32_t* __restrict__ 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 typedef int32_t v16i __attribute__((ext_vector_type(16)));
 
-// One wave per 32x32 output tile (I, J), I <= J, of C = U U restricted to the
-// k-blocks I..J where both factors can be non-zero; the epilogue masks with
-// U[I,J] and adds into T_H.  Operand fragments: lane l supplies row (l mod 32)
-// of the A tile and column (l mod 32) of the B tile, 16 consecutive k-bytes
-// starting at 16 * (l / 32); the same k-permutation is used for A and B.
+constexpr int kHK = 64;          // k-bytes staged per step
+constexpr int kHRow = kHK + 16;  // LDS row stride: 16-lane groups of 16-byte reads hit 64 distinct banks
+
+// T_H = sum over i < j of (U U)[i][j] U[i][j] with U the strictly upper
+// triangular adjacency of the heavy vertices in rank order (each heavy
+// triangle i < k < j once).  One block per 128 x 128 macro tile (I, J), I <= J,
+// of C = U U; because U is strictly upper triangular, only k in
+// [128 I, 128 J + 128) can contribute, and the k-loop covers exactly those
+// k-blocks.  Per step the block stages 128 rows x 64 k-bytes of U (rows of the
+// tile) and of U^T (columns of the tile) in LDS; each wave owns a 64 x 64
+// quarter as 2 x 2 tiles of v_mfma_i32_32x32x32_i8.  Operand fragments: lane l
+// supplies row (l mod 32) of the A tile and column (l mod 32) of the B tile,
+// 16 consecutive k-bytes starting at 16 (l / 32); A and B use the same
+// k-permutation.  The epilogue masks C with U and adds into T_H.
+// Macro tiles are enumerated column by column (t = J (J + 1) / 2 + I) and
+// dealt to the 8 XCDs in contiguous ranges, so blocks of one XCD share the
+// U^T panels of their columns in that XCD's L2.
 __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ U, const uint8_t* __restrict__ UT,
                                                      const int32_t* __restrict__ h_dev, int64_t* __restrict__ acc) {
+    __shared__ __attribute__((aligned(16))) uint8_t As[kHT * kHRow];
+    __shared__ __attribute__((aligned(16))) uint8_t Bs[kHT * kHRow];
     const int32_t h = h_dev[0];
-    if (h < 3) return;
-    const int32_t hp = (h + 31) / 32 * 32;
-    const int64_t nbk = hp / 32;
-    const int64_t ntiles = nbk * (nbk + 1) / 2;
-    for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < ntiles; t += (int64_t)gridDim.x * 4) {
-    // invert t = J (J + 1) / 2 + I
-    int64_t J = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while (J * (J + 1) / 2 > t) --J;
-    while ((J + 1) * (J + 2) / 2 <= t) ++J;
-    const int64_t I = t - J * (J + 1) / 2;
+    if (h < 3) return;  // block-uniform
+    const int64_t hp = heavy_pad(h);
+    const int64_t nm = hp / kHT;
+    const int64_t ntiles = nm * (nm + 1) / 2;
+    const int t = threadIdx.x;
+    const int w = t >> 6;
     const int lane = __lane_id();
-    const int r = lane & 31;
-    const int kh = lane >> 5;
-    const uint8_t* arow = U + (I * 32 + r) * (int64_t)hp + kh * 16;
-    const uint8_t* brow = UT + (J * 32 + r) * (int64_t)hp + kh * 16;
-    v16i c = {0};
-    for (int64_t kb = I; kb <= J; ++kb) {
-        const v4i a = *(const v4i*)(arow + kb * 32);
-        const v4i b = *(const v4i*)(brow + kb * 32);
-        c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
-    }
-    // accumulator element q of lane l: row 8*(q/4) + 4*(l/32) + q%4, column l%32
-    int64_t s = 0;
-    const int colj = (int)(J * 32) + r;
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;  // the wave's quarter of the macro tile
+    const int fr = lane & 31, fk = 16 * (lane >> 5);   // fragment row and k offset
+    const int lr = t >> 1, lc = (t & 1) * 32;          // staging: row and byte offset of this thread
+    // XCD-contiguous ranges: block b runs on XCD b mod 8 (gridDim.x is a multiple of 8)
+    const int64_t xcd = blockIdx.x & 7;
+    const int64_t per_xcd = gridDim.x >> 3;
+    const int64_t chunk = (ntiles + 7) / 8;
+    const int64_t t_end = min(ntiles, (xcd + 1) * chunk);
+    int64_t total = 0;
+    for (int64_t tt = xcd * chunk + (blockIdx.x >> 3); tt < t_end; tt += per_xcd) {
+        int64_t J = (int64_t)((sqrt(8.0 * (double)tt + 1.0) - 1.0) * 0.5);
+        while (J * (J + 1) / 2 > tt) --J;
+        while ((J + 1) * (J + 2) / 2 <= tt) ++J;
+        const int64_t I = tt - J * (J + 1) / 2;
+        const int64_t row0 = I * kHT, col0 = J * kHT;
+        const uint8_t* ga = U + (row0 + lr) * hp + lc;
+        const uint8_t* gb = UT + (col0 + lr) * hp + lc;
+        v16i c[2][2];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int row = (int)(I * 32) + 8 * (q >> 2) + 4 * kh + (q & 3);
-        s += (int64_t)c[q] * (int64_t)U[(int64_t)row * hp + colj];
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) c[i][j] = (v16i){0};
+        for (int64_t k0 = row0; k0 < col0 + kHT; k0 += kHK) {
+            const v4i a0 = *(const v4i*)(ga + k0);
+            const v4i a1 = *(const v4i*)(ga + k0 + 16);
+            const v4i b0 = *(const v4i*)(gb + k0);
+            const v4i b1 = *(const v4i*)(gb + k0 + 16);
+            __syncthreads();  // the previous step's fragment reads are done
+            *(v4i*)(As + lr * kHRow + lc) = a0;
+            *(v4i*)(As + lr * kHRow + lc + 16) = a1;
+            *(v4i*)(Bs + lr * kHRow + lc) = b0;
+            *(v4i*)(Bs + lr * kHRow + lc + 16) = b1;
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < kHK; ks += 32) {
+                v4i af[2], bf[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) af[i] = *(const v4i*)(As + (wr + 32 * i + fr) * kHRow + ks + fk);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) bf[j] = *(const v4i*)(Bs + (wc + 32 * j + fr) * kHRow + ks + fk);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        c[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[i], bf[j], c[i][j], 0, 0, 0);
+            }
+        }
+        // accumulator element q of lane l: row 8 (q / 4) + 4 (l / 32) + q mod 4, column l mod 32
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int64_t colj = col0 + wc + 32 * j + fr;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int64_t row = row0 + wr + 32 * i + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    total += (int64_t)c[i][j][q] * (int64_t)U[row * hp + colj];
+                }
+            }
     }
-    s = wave_sum(s);
-    if (lane == 0 && s) atomicAdd((unsigned long long*)&acc[kTH], (unsigned long long)s);
-    }
+    total = wave_sum(total);
+    if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTH], (unsigned long long)total);
 }
 
 }  // namespace
@@ -800,7 +855,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
 
     // host-side bounds for every launch (no read-back inside a count)
     const int64_t hmax = heavy_bound(n, g->m, cfg.heavy_num, cfg.heavy_den);
-    const int64_t hp_max = (hmax + 31) / 32 * 32;
+    const int64_t hp_max = heavy_pad(hmax);
     if (hp_max * hp_max > ((int64_t)16 << 30))
         fail(TC_ERR_OVERFLOW, "heavy block bound exceeds 16 GiB: raise the heavy threshold");
     const int64_t items_max = 2 * n + E2 / kJL + 2;
@@ -933,8 +988,12 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         TC_LAUNCH("heavy_pack", k_heavy_pack, dim3((unsigned)hmax), dim3(256), 0, s, (const int32_t*)horder.get(),
                   h_dev, (const int32_t*)rpO.get(), (const int32_t*)colO.get(), (const int32_t*)hidx.get(), U.get(),
                   UT.get());
-        TC_LAUNCH("heavy_mfma", k_heavy_mfma, dim3((unsigned)(num_cus() * 8)), dim3(256), 0, s,
-                  (const uint8_t*)U.get(), (const uint8_t*)UT.get(), h_dev, acc);
+        // one block per macro tile up to 8 per CU, a multiple of 8 (one share per XCD)
+        const int64_t nm_max = hp_max / kHT;
+        const int64_t tiles_max = nm_max * (nm_max + 1) / 2;
+        const int64_t mblocks = std::min<int64_t>((int64_t)num_cus() * 8, (tiles_max + 7) / 8 * 8);
+        TC_LAUNCH("heavy_mfma", k_heavy_mfma, dim3((unsigned)mblocks), dim3(256), 0, s, (const uint8_t*)U.get(),
+                  (const uint8_t*)UT.get(), h_dev, acc);
     }
     TC_LAUNCH("finish", k_finish, dim3(1), dim3(64), 0, s, mp_dev, (const int32_t*)hpos.get() + n, acc);
 }
@@ -979,7 +1038,7 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     if (plan.dcap_global) b += rb(8 * items_max) + rb(4 * (int64_t)num_cus() * large_block_words(plan.dcap_global));
     const int64_t hmax = heavy_bound(n, m, cfg.heavy_num, cfg.heavy_den);
     if (hmax >= 3) {
-        const int64_t hp = (hmax + 31) / 32 * 32;
+        const int64_t hp = heavy_pad(hmax);
         b += 2 * rb(4 * hmax) + rb(4 * n) + 2 * rb(hp * hp);
     }
     return b;

@@ -125,3 +125,26 @@ def test_cl20_batched_median_of_means_matches_golden(gpu):
     assert [c["triangles"] for c in per] == gold["triangles"]
     assert mom == gold["median_of_means"]
     assert gpu.tc_count_exact(g)["triangles"] == gold["exact"]["triangles"]
+
+
+@pytest.mark.parametrize("h", [1000, 2048, 4096])
+def test_top_degree_block_all_heavy_matches_oracle(gpu, rmat22, h):
+    # the dense subgraph induced by the h highest-degree vertices of R-MAT s22,
+    # counted with every vertex heavy: the whole count runs in the int8-MFMA
+    # block (h = 1000 leaves a ragged last macro tile)
+    import torch
+    n, s, d, g = rmat22
+    og = oracle.normalise(n, s, d)
+    deg = np.diff(og[1])
+    order = np.lexsort((np.arange(n), deg))[::-1][:h]
+    lab = np.full(n, -1, np.int64)
+    lab[order] = np.arange(h)
+    keep = (lab[s] >= 0) & (lab[d] >= 0)
+    hs, hd = lab[s[keep]].astype(np.int32), lab[d[keep]].astype(np.int32)
+    want = oracle.count(oracle.normalise(h, hs, hd))
+    sg = gpu.tc_build_csr(h, torch.from_numpy(hs).cuda(), torch.from_numpy(hd).cuda())
+    c = gpu.tc_count_exact(sg, heavy=(0, 1))
+    _log("top-%d block: m=%d T=%d n_heavy=%d" % (h, c["m"], c["triangles"], c["n_heavy"]))
+    assert c["triangles"] == want and c["heavy"] == want and c["light"] == 0
+    assert gpu.tc_count_exact(sg)["triangles"] == want
+    sg.free()
