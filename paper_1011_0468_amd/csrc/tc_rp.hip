@@ -9,6 +9,7 @@
 //   rp_bits : word[i] = mix64(mix64(c << 32 | i) ^ salt)                 (n words)
 //   rp_spmm : Y[i][b] = sum_{j in N(i)} x_b[j] = deg i - 2 #{j in N(i) : bit b of word[j]}
 //   rp_dot  : q[b]    = sum over CSR entries (i, j) of Y[i][b] * Y[j][b]
+//                     = 2 * sum over the entries with j > i
 //
 // Both sweeps are edge-parallel: wave w owns CSR entries [w L, (w+1) L), so a
 // hub row is split over many waves.  rp_dot is a plain sum over entries.  In
@@ -41,64 +42,81 @@ __global__ void __launch_bounds__(256) k_rp_spmm(int64_t E2, const int32_t* __re
                                                   const int32_t* __restrict__ src, const int32_t* __restrict__ col,
                                                   const uint64_t* __restrict__ words, int32_t* __restrict__ Y) {
     const int lane = __lane_id();
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t e0 = w * kRpRange;
     if (e0 >= E2) return;
     const int64_t e1 = e0 + kRpRange < E2 ? e0 + kRpRange : E2;
-    int32_t cur = src[e0];
+    int32_t cur = __builtin_amdgcn_readfirstlane(src[e0]);
     int32_t cnt = 0, ones = 0;
-    for (int64_t e = e0; e < e1; e += kRpUnroll) {
-        int32_t ii[kRpUnroll];
-        uint64_t ww[kRpUnroll];
+    for (int64_t eb = e0; eb < e1; eb += 64) {
+        // 64 entries per coalesced load; entry k of the batch is read from lane k
+        const int64_t el = eb + lane;
+        const int32_t vi = el < e1 ? src[el] : -1;
+        const int32_t vj = el < e1 ? col[el] : 0;
+        for (int k0 = 0; k0 < 64; k0 += kRpUnroll) {
+            int32_t ii[kRpUnroll];
+            uint64_t ww[kRpUnroll];
 #pragma unroll
-        for (int k = 0; k < kRpUnroll; ++k) {
-            const int64_t ek = e + k;
-            ii[k] = ek < e1 ? src[ek] : -1;
-            ww[k] = ek < e1 ? words[col[ek]] : 0ull;
-        }
-#pragma unroll
-        for (int k = 0; k < kRpUnroll; ++k) {
-            if (ii[k] < 0) break;  // wave-uniform: past the range end
-            if (ii[k] != cur) {
-                rp_flush(cur, cnt, ones, e0, e1, row_ptr, Y, lane);
-                cur = ii[k];
-                cnt = 0;
-                ones = 0;
+            for (int k = 0; k < kRpUnroll; ++k) {
+                ii[k] = __builtin_amdgcn_readlane(vi, k0 + k);
+                ww[k] = ii[k] >= 0 ? words[__builtin_amdgcn_readlane(vj, k0 + k)] : 0ull;
             }
-            ++cnt;
-            ones += (int32_t)((ww[k] >> lane) & 1ull);
+#pragma unroll
+            for (int k = 0; k < kRpUnroll; ++k) {
+                if (ii[k] < 0) break;  // wave-uniform: past the range end
+                if (ii[k] != cur) {
+                    rp_flush(cur, cnt, ones, e0, e1, row_ptr, Y, lane);
+                    cur = ii[k];
+                    cnt = 0;
+                    ones = 0;
+                }
+                ++cnt;
+                ones += (int32_t)((ww[k] >> lane) & 1ull);
+            }
         }
     }
     rp_flush(cur, cnt, ones, e0, e1, row_ptr, Y, lane);
 }
 
+// q[b] = sum over CSR entries (i, j) of Y[i][b] Y[j][b] = 2 * the sum over the
+// entries with j > i (A is symmetric without loops), so only those entries
+// gather the 256-byte row Y[j]; the entry indices are wave-uniform and kept in
+// scalar registers (read from lanes of one coalesced load), so a skipped
+// entry issues no load.
 __global__ void __launch_bounds__(256) k_rp_dot(int64_t E2, const int32_t* __restrict__ src,
                                                  const int32_t* __restrict__ col, const int32_t* __restrict__ Y,
                                                  int64_t* __restrict__ q) {
     const int lane = __lane_id();
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t w = (int64_t)blockIdx.x * 4 + wv;
     const int64_t e0 = w * kRpRange;
     int64_t acc = 0;
     if (e0 < E2) {
         const int64_t e1 = e0 + kRpRange < E2 ? e0 + kRpRange : E2;
         int32_t cur = -1, ycur = 0;
-        for (int64_t e = e0; e < e1; e += kRpUnroll) {
-            int32_t ii[kRpUnroll], yj[kRpUnroll];
+        for (int64_t eb = e0; eb < e1; eb += 64) {
+            // 64 entries per coalesced load; entry k of the batch is read from lane k
+            const int64_t el = eb + lane;
+            const int32_t vi = el < e1 ? src[el] : -1;
+            const int32_t vj = el < e1 ? col[el] : -1;
+            for (int k0 = 0; k0 < 64; k0 += kRpUnroll) {
+                int32_t ii[kRpUnroll], jj[kRpUnroll], yj[kRpUnroll];
 #pragma unroll
-            for (int k = 0; k < kRpUnroll; ++k) {
-                const int64_t ek = e + k;
-                ii[k] = ek < e1 ? src[ek] : -1;
-                yj[k] = ek < e1 ? Y[(int64_t)col[ek] * 64 + lane] : 0;
-            }
-#pragma unroll
-            for (int k = 0; k < kRpUnroll; ++k) {
-                if (ii[k] < 0) break;
-                if (ii[k] != cur) {
-                    cur = ii[k];
-                    ycur = Y[(int64_t)cur * 64 + lane];
+                for (int k = 0; k < kRpUnroll; ++k) {
+                    ii[k] = __builtin_amdgcn_readlane(vi, k0 + k);
+                    jj[k] = __builtin_amdgcn_readlane(vj, k0 + k);
                 }
-                acc += (int64_t)ycur * (int64_t)yj[k];
+#pragma unroll
+                for (int k = 0; k < kRpUnroll; ++k) yj[k] = jj[k] > ii[k] ? Y[(int64_t)jj[k] * 64 + lane] : 0;
+#pragma unroll
+                for (int k = 0; k < kRpUnroll; ++k) {
+                    if (jj[k] <= ii[k]) continue;  // lower entry, or past the range end (-1, -1)
+                    if (ii[k] != cur) {
+                        cur = ii[k];
+                        ycur = Y[(int64_t)cur * 64 + lane];
+                    }
+                    acc += (int64_t)ycur * (int64_t)yj[k];
+                }
             }
         }
     }
@@ -107,7 +125,7 @@ __global__ void __launch_bounds__(256) k_rp_dot(int64_t E2, const int32_t* __res
     __syncthreads();
     if (wv == 0) {
         const int64_t s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-        if (s) atomicAdd((unsigned long long*)&q[lane], (unsigned long long)s);
+        if (s) atomicAdd((unsigned long long*)&q[lane], (unsigned long long)(2 * s));
     }
 }
 
