@@ -88,6 +88,11 @@ __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__
     }
 }
 
+// int32 words of one 4-wave block's table, list staging and flags (16-byte multiple)
+__host__ __device__ inline int64_t large_block_words(int32_t dcap) {
+    return (4 * (int64_t)dcap + 2 * kJL + 1 + 256 * kU + 3) / 4 * 4;
+}
+
 // Heavy block: U is stored padded to a multiple of the MFMA macro tile edge.
 constexpr int kHT = 128;
 __host__ __device__ inline int64_t heavy_pad(int64_t h) { return (h + kHT - 1) / kHT * kHT; }
@@ -403,17 +408,18 @@ __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const 
 }
 
 // Owners and gathers of one super-strip of 64 * U positions starting at g0
-// (< b): position g lies in list j (P[j] <= g < P[j+1]) at offset g - P[j] of
-// the list starting at colO[S[j]]; nl lists, none empty, so P is strictly
-// increasing.  jlo is the owner of g0 on entry (of g0 + 64U - 1 on exit).
-// When the whole super-strip lies in list jlo every lane owns jlo; otherwise
-// the lists starting inside it (at most 64U, those after jlo) are marked at
-// their start offsets in `mark` (64U ints of per-wave LDS) and each lane's
-// owner is the running maximum of the marks: one 64-lane max-scan per strip.
-// Loads are issued for every lane (clamped to the owner's first entry past b)
-// so the caller can keep them in flight.  Whole wave.
+// (< b): position g lies in list j (P[j] <= g < P[j+1]) and reads
+// colO[D[j] + g], D[j] being the list's start in colO minus P[j]; nl lists,
+// none empty, so P is strictly increasing.  On entry jlo owns position g0 - 1
+// (or g0), on exit position g0 + 64U - 1.  When no list starts inside the
+// super-strip every lane owns jlo.  Otherwise the lists starting inside it (at
+// most 64U, those after jlo) flag their start offsets in `mark` (64U ints of
+// per-wave memory, all zero between calls), and the owner of position
+// g0 + 64k + lane is jlo plus the number of flags at offsets <= 64k + lane:
+// one ballot and one mbcnt per strip of 64.  Lanes past b issue no load.
+// Whole wave.
 template <int U, bool GLOBAL>
-__device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* S, int nl, int32_t g0, int32_t b,
+__device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D, int nl, int32_t g0, int32_t b,
                                               const int32_t* __restrict__ colO, int32_t* mark, int lane, int& jlo,
                                               int32_t (&x)[U]) {
     int32_t o[U];
@@ -423,42 +429,32 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* S
         for (int k = 0; k < U; ++k) o[k] = jlo;
     } else {
 #pragma unroll
-        for (int k = 0; k < U; ++k) mark[lane + 64 * k] = -1;
-        wave_sync<GLOBAL>();
-#pragma unroll
         for (int k = 0; k < U; ++k) {
             const int j = jlo + 1 + lane + 64 * k;
             if (j < nl) {
-                const int32_t off = P[j] - g0;  // >= 0: list jlo + 1 starts after position g0 - 1
-                if (off < 64 * U) mark[off] = j;
+                const int32_t off = P[j] - g0;  // >= 0: list jlo + 1 starts at g0 or later
+                if (off < 64 * U) mark[off] = 1;
             }
         }
         wave_sync<GLOBAL>();
-#pragma unroll
-        for (int k = 0; k < U; ++k) o[k] = mark[lane + 64 * k];
-#pragma unroll
-        for (int dd = 1; dd < 64; dd <<= 1) {
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int32_t q = __shfl_up(o[k], dd, 64);
-                if (lane >= dd) o[k] = q > o[k] ? q : o[k];
-            }
-        }
-        int32_t carry = jlo;
+        int32_t base = jlo;
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            o[k] = o[k] > carry ? o[k] : carry;
-            carry = __shfl(o[k], 63, 64);
+            const int32_t f = mark[lane + 64 * k];
+            const uint64_t M = ballot64(f != 0);
+            const int32_t below = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(M >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
+            o[k] = base + below + f;
+            base += (int32_t)__popcll(M);
+            mark[lane + 64 * k] = 0;
         }
-        jlo = carry;
-        wave_sync<GLOBAL>();  // mark reads done before the next super-strip resets it
+        jlo = base;
+        wave_sync<GLOBAL>();  // flags cleared before the next super-strip sets any
     }
 #pragma unroll
     for (int k = 0; k < U; ++k) {
         const int32_t g = g0 + lane + 64 * k;
-        const int32_t off = g < b ? g - P[o[k]] : 0;
-        const int32_t v = colO[S[o[k]] + off];
-        x[k] = g < b ? v : -1;
+        x[k] = g < b ? colO[D[o[k]] + g] : -1;
     }
 }
 
@@ -466,7 +462,7 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* S
 // (layout as in gather_strips).  Software-pipelined: the gathers of the next
 // super-strip are issued before the hash probes of the current one.
 template <int U, bool GLOBAL>
-__device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* S, int nl, int32_t a, int32_t b,
+__device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D, int nl, int32_t a, int32_t b,
                                               const int32_t* __restrict__ colO, const int32_t* tab, int lg,
                                               int32_t* mark, int lane) {
     int32_t cnt = 0;
@@ -475,10 +471,10 @@ __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* S
     int32_t xc[U], xn[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) xn[k] = -1;
-    gather_strips<U, GLOBAL>(P, S, nl, a, b, colO, mark, lane, jlo, xc);
+    gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, xc);
     for (int32_t g0 = a; g0 < b; g0 += 64 * U) {
         const int32_t gn = g0 + 64 * U;
-        if (gn < b) gather_strips<U, GLOBAL>(P, S, nl, gn, b, colO, mark, lane, jlo, xn);
+        if (gn < b) gather_strips<U, GLOBAL>(P, D, nl, gn, b, colO, mark, lane, jlo, xn);
         cnt += probe_many<U>(tab, lg, xc);
 #pragma unroll
         for (int k = 0; k < U; ++k) xc[k] = xn[k];
@@ -507,10 +503,11 @@ __device__ __forceinline__ void build_hash(int32_t rs, int32_t d, const int32_t*
 // Stage the packed entries L[0..cnt) (cnt <= kJL) of an anchor's iterated
 // list: (start in colO, length) of the list streamed for each entry, length 0
 // when the pair is closed from the other side.  Non-empty lists are compacted
-// in entry order into S (start) and P (exclusive prefix of lengths, P[nl] =
-// total).  Returns nl; *total receives the number of positions.
+// in entry order into P (exclusive prefix of lengths, P[nl] = total) and D
+// (start in colO minus P, so position g of list j reads colO[D[j] + g]).
+// Returns nl; *total receives the number of positions.
 template <int NT>
-__device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32_t cnt, int32_t* P, int32_t* S,
+__device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32_t cnt, int32_t* P, int32_t* D,
                                                int32_t* red, int t, int32_t* total) {
     constexpr int R = (kJL + NT - 1) / NT;
     int32_t st[R], ln[R];
@@ -543,7 +540,7 @@ __device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         if (ln[k] > 0) {
-            S[nex] = st[k];
+            D[nex] = st[k] - ex;
             P[nex] = ex;
             ex += ln[k];
             ++nex;
@@ -556,7 +553,7 @@ __device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32
 
 // One wave per item, persistent over items with a static stride.  Item
 // (x, r): anchor x, kind u (x >= 0) or v (encoded ~x), entries r*kJL.. of the
-// iterated list.  LDS per wave: hash (2*DS slots), P (kJL+1), S (kJL).
+// iterated list.  LDS per wave: hash (4*DS slots), P (kJL+1), D (kJL), flags (64 kU).
 template <int DS>
 __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ items,
                                                       const int32_t* __restrict__ n_items_dev,
@@ -570,8 +567,10 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
     const int lane = __lane_id();
     int32_t* tab = lds[w];
     int32_t* P = tab + HS_MAX;
-    int32_t* S = P + kJL + 1;
-    int32_t* mark = S + kJL;
+    int32_t* D = P + kJL + 1;
+    int32_t* mark = D + kJL;
+#pragma unroll
+    for (int k = 0; k < kU; ++k) mark[lane + 64 * k] = 0;  // flags stay zero between super-strips
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
     const int64_t n_items = n_items_dev[0];
@@ -595,9 +594,9 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         wave_lds_sync();
         build_hash<64>(rs, d, colO, tab, lg, lane);
         int32_t W;
-        const int32_t nl = stage_lists<64>(L + j0, cnt, P, S, nullptr, lane, &W);
+        const int32_t nl = stage_lists<64>(L + j0, cnt, P, D, nullptr, lane, &W);
         wave_lds_sync();
-        total += close_flat<kU, false>(P, S, nl, 0, W, colO, tab, lg, mark, lane);
+        total += close_flat<kU, false>(P, D, nl, 0, W, colO, tab, lg, mark, lane);
         wave_lds_sync();
     }
     total = wave_sum(total);
@@ -618,15 +617,18 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
                                                       int32_t* __restrict__ gscratch, int64_t* __restrict__ acc) {
     extern __shared__ __attribute__((aligned(16))) int32_t dyn[];
     __shared__ int32_t red[5];
-    // layout: hash table (next_pow2(2d) <= 2 dcap slots), P (kJL + 1), S (kJL), marks (4 x 64 kU)
-    const int64_t per_block = (4 * (int64_t)dcap + 2 * kJL + 1 + 256 * kU + 3) / 4 * 4;
+    // layout: hash table (4 next_pow2(d) <= 4 dcap slots), P (kJL + 1), D (kJL), flags (4 x 64 kU)
+    const int64_t per_block = large_block_words(dcap);
     int32_t* base = GLOBAL ? gscratch + (int64_t)blockIdx.x * per_block : dyn;
     int32_t* tab = base;
     int32_t* P = base + 4 * dcap;
-    int32_t* S = P + kJL + 1;
+    int32_t* D = P + kJL + 1;
     const int t = threadIdx.x;
     const int w = t >> 6;
     const int lane = __lane_id();
+    int32_t* mark = D + kJL + 64 * kU * w;
+#pragma unroll
+    for (int k = 0; k < kU; ++k) mark[lane + 64 * k] = 0;  // flags stay zero between super-strips
     const int64_t n_items = n_items_dev[0];
     int64_t total = 0;
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -648,12 +650,12 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         __syncthreads();
         build_hash<256>(rs, d, colO, tab, lg, t);
         int32_t W;
-        const int32_t nl = stage_lists<256>(L + j0, cnt, P, S, red, t, &W);
+        const int32_t nl = stage_lists<256>(L + j0, cnt, P, D, red, t, &W);
         __syncthreads();
         const int32_t q = (W + 3) / 4;
         const int32_t a = min(w * q, W);
         const int32_t b = min(a + q, W);
-        total += close_flat<kU, GLOBAL>(P, S, nl, a, b, colO, tab, lg, S + kJL + 64 * kU * w, lane);
+        total += close_flat<kU, GLOBAL>(P, D, nl, a, b, colO, tab, lg, mark, lane);
         __syncthreads();
     }
     total = wave_sum(total);
@@ -841,8 +843,6 @@ static LightPlan light_plan(int64_t m, int32_t maxd, const CountConfig& cfg) {
     return pl;
 }
 
-// int32 words of one block's table, list staging and marks
-static int64_t large_block_words(int32_t dcap) { return (4 * (int64_t)dcap + 2 * kJL + 1 + 256 * kU + 3) / 4 * 4; }
 
 void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
                    hipStream_t s, int64_t* acc) {
@@ -949,7 +949,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)cnt.get(),
                   (const int32_t*)base.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
                   (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
-        // tab: 4 * next_pow2(d) <= 4 * dcap slots, P: kJL+1, S: kJL, marks: 4*64*kU (16-byte multiple)
+        // tab: 4 * next_pow2(d) <= 4 * dcap slots, P: kJL+1, D: kJL, flags: 4*64*kU (16-byte multiple)
         const size_t per_block = (size_t)large_block_words(dcap);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
         if (!global) {
