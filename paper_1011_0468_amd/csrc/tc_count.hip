@@ -370,38 +370,54 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ void wave_lds_sync() { wave_sync<false>(); }
 
-// Membership tests of up to U keys (x[k] < 0: no key) against the bucketed
-// table: one 16-byte read per key resolves it unless the bucket is full
-// without it; the few unresolved keys continue bucket by bucket.
+// Membership tests of the keys x[k] of the lanes in the wave mask vm[k]
+// against the bucketed table; returns the number of hits in the whole wave
+// (wave-uniform).  One 16-byte read per key resolves it unless the bucket is
+// full without it.  Slots of a bucket fill in order (an insert tries slot s
+// only after finding slots 0..s-1 full) and never empty, so a bucket has a
+// free slot iff its last slot is free.  Every x[k] is a vertex id (>= 0), also
+// in lanes outside vm[k].
 template <int U>
-__device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const int32_t (&x)[U]) {
+__device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const int32_t (&x)[U],
+                                              const uint64_t (&vm)[U]) {
     const uint32_t mask = (1u << lg) - 1;
     const int4* t4 = reinterpret_cast<const int4*>(tab);
     uint32_t bk[U];
     int32_t found = 0;
-    uint32_t live = 0;
+    uint64_t live[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) bk[k] = hslot(x[k] >= 0 ? x[k] : 0, lg) & mask;
+    for (int k = 0; k < U; ++k) bk[k] = hslot(x[k], lg);  // < 2^lg
     int4 e[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) e[k] = t4[bk[k]];
+    uint64_t any = 0;
 #pragma unroll
     for (int k = 0; k < U; ++k) {
         const int32_t v = x[k];
-        const bool hit = e[k].x == v || e[k].y == v || e[k].z == v || e[k].w == v;
-        const bool open = (e[k].x | e[k].y | e[k].z | e[k].w) < 0;  // ids are >= 0, empty slots are -1
-        found += (v >= 0 && hit) ? 1 : 0;
-        live |= (v >= 0 && !hit && !open ? 1u : 0u) << k;
+        // one compare per slot straight into a wave mask (no per-lane booleans)
+        const uint64_t hit =
+            (ballot64(e[k].x == v) | ballot64(e[k].y == v) | ballot64(e[k].z == v) | ballot64(e[k].w == v)) & vm[k];
+        const uint64_t full = ballot64(e[k].w >= 0);
+        found += (int32_t)__popcll(hit);
+        live[k] = vm[k] & full & ~hit;
+        any |= live[k];
     }
-    while (live) {  // rare: home bucket full without the key
+    if (any) {  // rare: home bucket full without the key
+        const int lane = __lane_id();
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            if (!((live >> k) & 1u)) continue;
-            bk[k] = (bk[k] + 1) & mask;
-            const int4 f = t4[bk[k]];
-            const int32_t v = x[k];
-            if (f.x == v || f.y == v || f.z == v || f.w == v) { ++found; live &= ~(1u << k); }
-            else if ((f.x | f.y | f.z | f.w) < 0) live &= ~(1u << k);
+            bool on = (live[k] >> lane) & 1ull;
+            while (ballot64(on)) {
+                int32_t hitl = 0;
+                if (on) {
+                    bk[k] = (bk[k] + 1) & mask;
+                    const int4 f = t4[bk[k]];
+                    const int32_t v = x[k];
+                    if (f.x == v || f.y == v || f.z == v || f.w == v) { hitl = 1; on = false; }
+                    else if (f.w < 0) on = false;
+                }
+                found += (int32_t)__popcll(ballot64(hitl != 0));
+            }
         }
     }
     return found;
@@ -416,12 +432,11 @@ __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const 
 // most 64U, those after jlo) flag their start offsets in `mark` (64U ints of
 // per-wave memory, all zero between calls), and the owner of position
 // g0 + 64k + lane is jlo plus the number of flags at offsets <= 64k + lane:
-// one ballot and one mbcnt per strip of 64.  Lanes past b issue no load.
-// Whole wave.
+// one ballot and one mbcnt per strip of 64.  Whole wave.
 template <int U, bool GLOBAL>
 __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D, int nl, int32_t g0, int32_t b,
                                               const int32_t* __restrict__ colO, int32_t* mark, int lane, int& jlo,
-                                              int32_t (&x)[U]) {
+                                              int32_t (&x)[U], uint64_t (&vm)[U]) {
     int32_t o[U];
     const int32_t nxt = jlo + 1 < nl ? P[jlo + 1] : INT32_MAX;
     if (nxt >= g0 + 64 * U) {  // wave-uniform: one list covers the super-strip
@@ -451,16 +466,21 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D
         jlo = base;
         wave_sync<GLOBAL>();  // flags cleared before the next super-strip sets any
     }
+    // every lane loads (lanes past b read colO[0], which exists whenever there
+    // are positions) and nothing consumes the loaded values before the probe,
+    // so these loads stay in flight across the caller's other work
 #pragma unroll
     for (int k = 0; k < U; ++k) {
         const int32_t g = g0 + lane + 64 * k;
-        x[k] = g < b ? colO[D[o[k]] + g] : -1;
+        x[k] = colO[g < b ? D[o[k]] + g : 0];
+        vm[k] = ballot64(g < b);
     }
 }
 
 // Closure tests for positions [a, b) of the concatenated streamed lists
-// (layout as in gather_strips).  Software-pipelined: the gathers of the next
-// super-strip are issued before the hash probes of the current one.
+// (layout as in gather_strips); returns the wave's number of hits.  Software-pipelined with two register sets:
+// the gathers of the next super-strip are issued, unconditionally, before the
+// hash probes of the current one, and no register copy waits on them.
 template <int U, bool GLOBAL>
 __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D, int nl, int32_t a, int32_t b,
                                               const int32_t* __restrict__ colO, const int32_t* tab, int lg,
@@ -468,16 +488,16 @@ __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D
     int32_t cnt = 0;
     if (a >= b) return 0;
     int jlo = find_list(P, nl, a);
-    int32_t xc[U], xn[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) xn[k] = -1;
-    gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, xc);
-    for (int32_t g0 = a; g0 < b; g0 += 64 * U) {
-        const int32_t gn = g0 + 64 * U;
-        if (gn < b) gather_strips<U, GLOBAL>(P, D, nl, gn, b, colO, mark, lane, jlo, xn);
-        cnt += probe_many<U>(tab, lg, xc);
-#pragma unroll
-        for (int k = 0; k < U; ++k) xc[k] = xn[k];
+    int32_t xa[U], xb[U];
+    uint64_t va[U], vb[U];
+    gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, xa, va);
+    for (int32_t g0 = a;; g0 += 2 * 64 * U) {
+        gather_strips<U, GLOBAL>(P, D, nl, g0 + 64 * U, b, colO, mark, lane, jlo, xb, vb);
+        cnt += probe_many<U>(tab, lg, xa, va);
+        if (g0 + 64 * U >= b) break;
+        gather_strips<U, GLOBAL>(P, D, nl, g0 + 2 * 64 * U, b, colO, mark, lane, jlo, xa, va);
+        cnt += probe_many<U>(tab, lg, xb, vb);
+        if (g0 + 2 * 64 * U >= b) break;
     }
     return cnt;
 }
@@ -596,10 +616,9 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         int32_t W;
         const int32_t nl = stage_lists<64>(L + j0, cnt, P, D, nullptr, lane, &W);
         wave_lds_sync();
-        total += close_flat<kU, false>(P, D, nl, 0, W, colO, tab, lg, mark, lane);
+        total += close_flat<kU, false>(P, D, nl, 0, W, colO, tab, lg, mark, lane);  // wave-uniform
         wave_lds_sync();
     }
-    total = wave_sum(total);
     if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTL], (unsigned long long)total);
 }
 
@@ -655,10 +674,9 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         const int32_t q = (W + 3) / 4;
         const int32_t a = min(w * q, W);
         const int32_t b = min(a + q, W);
-        total += close_flat<kU, GLOBAL>(P, D, nl, a, b, colO, tab, lg, mark, lane);
+        total += close_flat<kU, GLOBAL>(P, D, nl, a, b, colO, tab, lg, mark, lane);  // wave-uniform
         __syncthreads();
     }
-    total = wave_sum(total);
     if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTL], (unsigned long long)total);
 }
 
