@@ -437,11 +437,17 @@ template <int U, bool GLOBAL>
 __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D, int nl, int32_t g0, int32_t b,
                                               const int32_t* __restrict__ colO, int32_t* mark, int lane, int& jlo,
                                               int32_t (&x)[U], uint64_t (&vm)[U]) {
-    int32_t o[U];
+    // every lane loads (lanes past b read colO[0], which exists whenever there
+    // are positions) and nothing consumes the loaded values before the probe,
+    // so these loads stay in flight across the caller's other work
     const int32_t nxt = jlo + 1 < nl ? P[jlo + 1] : INT32_MAX;
     if (nxt >= g0 + 64 * U) {  // wave-uniform: one list covers the super-strip
+        const int32_t d0 = D[jlo];
 #pragma unroll
-        for (int k = 0; k < U; ++k) o[k] = jlo;
+        for (int k = 0; k < U; ++k) {
+            const int32_t g = g0 + lane + 64 * k;
+            x[k] = colO[g < b ? d0 + g : 0];
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -453,28 +459,27 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D
         }
         wave_sync<GLOBAL>();
         int32_t base = jlo;
+        int32_t dk[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int32_t f = mark[lane + 64 * k];
             const uint64_t M = ballot64(f != 0);
             const int32_t below = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(M >> 32),
                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
-            o[k] = base + below + f;
+            dk[k] = D[base + below + f];  // the owner's offset (owner index < nl)
             base += (int32_t)__popcll(M);
             mark[lane + 64 * k] = 0;
         }
         jlo = base;
         wave_sync<GLOBAL>();  // flags cleared before the next super-strip sets any
-    }
-    // every lane loads (lanes past b read colO[0], which exists whenever there
-    // are positions) and nothing consumes the loaded values before the probe,
-    // so these loads stay in flight across the caller's other work
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-        const int32_t g = g0 + lane + 64 * k;
-        x[k] = colO[g < b ? D[o[k]] + g : 0];
-        vm[k] = ballot64(g < b);
+        for (int k = 0; k < U; ++k) {
+            const int32_t g = g0 + lane + 64 * k;
+            x[k] = colO[g < b ? dk[k] + g : 0];
+        }
     }
+#pragma unroll
+    for (int k = 0; k < U; ++k) vm[k] = ballot64(g0 + lane + 64 * k < b);
 }
 
 // Closure tests for positions [a, b) of the concatenated streamed lists
