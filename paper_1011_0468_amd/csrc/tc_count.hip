@@ -41,6 +41,9 @@ unsigned grid_for(int64_t N, int threads) {
     return b ? b : 1;
 }
 
+// Blocks of the classification pass (one partial of its statistics each).
+constexpr unsigned kClassifyBlocks = 2048;
+
 // Entries of an iterated list processed by one work item.
 constexpr int kJL = 256;
 // Largest anchor out-degree whose table the block kernel keeps in LDS.
@@ -57,33 +60,50 @@ constexpr int kU = 4;
 // its lower-ranked end) and one down entry (in the row of its higher end).
 // E2 bounds the buffers; E2_dev (if not null) holds the number of valid
 // entries, which may be smaller (a compacted sample in buffers sized for the
-// full graph): words past it get zero bits.
+// full graph): words past it get zero bits.  Each wave takes 4 words (256
+// entries) per step and issues all their loads before the first use, the
+// degree gathers likewise.
 __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__ src, const int32_t* __restrict__ col,
                                                       int64_t E2, const int32_t* __restrict__ E2_dev,
-                                                      const uint64_t* __restrict__ keep,
                                                       const int32_t* __restrict__ degp, uint64_t* __restrict__ ubits,
                                                       int32_t* __restrict__ ucnt, uint64_t* __restrict__ dbits,
                                                       int32_t* __restrict__ dcnt) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int lane = __lane_id();
+    const int64_t NW = (E2 + 63) / 64;
     const int64_t valid = E2_dev ? (int64_t)E2_dev[0] : E2;
-    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < E2; e0 += stride) {
-        const int64_t e = e0 + threadIdx.x;
-        bool up = false, dn = false;
-        if (e < valid) {
-            const bool k = keep ? ((keep[e >> 6] >> (e & 63)) & 1ull) : true;
-            if (k) {
-                const int32_t u = src[e], v = col[e];
-                up = rank_below(degp[u], u, degp[v], v);
-                dn = !up;
-            }
+    const int64_t last = valid > 0 ? valid - 1 : 0;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t w0 = wave * 4; w0 < NW; w0 += nwaves * 4) {
+        int32_t u[4], v[4];
+        bool in[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t e = (w0 + k) * 64 + lane;
+            const int64_t ec = e < last ? e : last;  // loads stay inside the buffers
+            in[k] = e < valid;
+            const int32_t a = src[ec], c = col[ec];
+            u[k] = in[k] ? a : 0;  // vertex 0 exists whenever a count runs
+            v[k] = in[k] ? c : 0;
         }
-        const uint64_t bu = ballot64(up);
-        const uint64_t bd = ballot64(dn);
-        if (__lane_id() == 0 && e < E2) {
-            ubits[e >> 6] = bu;
-            ucnt[e >> 6] = __popcll(bu);
-            dbits[e >> 6] = bd;
-            dcnt[e >> 6] = __popcll(bd);
+        int32_t du[4], dv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            du[k] = degp[u[k]];
+            dv[k] = degp[v[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool up = in[k] && rank_below(du[k], u[k], dv[k], v[k]);
+            const bool dn = in[k] && !up;
+            const uint64_t bu = ballot64(up);
+            const uint64_t bd = ballot64(dn);
+            if (lane == k && w0 + k < NW) {
+                ubits[w0 + k] = bu;
+                ucnt[w0 + k] = __popcll(bu);
+                dbits[w0 + k] = bd;
+                dcnt[w0 + k] = __popcll(bd);
+            }
         }
     }
 }
@@ -219,7 +239,7 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
                                                    const int64_t* __restrict__ Wu, const int64_t* __restrict__ Wv,
                                                    int32_t small_dmax, int32_t* __restrict__ nsm,
                                                    int32_t* __restrict__ nlg, int32_t* __restrict__ nhg,
-                                                   int64_t* __restrict__ acc) {
+                                                   int64_t* __restrict__ part) {
     int64_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sources, out, wedges, probes, bytes_s, bytes_l, items_s, items_l
     int64_t dmax = 0;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
@@ -254,16 +274,14 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
         red[wv_][8] = dmax;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    // one partial per block (no contended atomics); k_finish folds them
+    if (threadIdx.x < 9) {
+        int64_t v = red[0][threadIdx.x];
         for (int w = 1; w < 4; ++w) {
-            for (int q = 0; q < 8; ++q) red[0][q] += red[w][q];
-            red[0][8] = red[w][8] > red[0][8] ? red[w][8] : red[0][8];
+            const int64_t o = red[w][threadIdx.x];
+            v = threadIdx.x == 8 ? (o > v ? o : v) : v + o;
         }
-        const int slot[8] = {kLightSources, kLightOut, kWedges, kProbes, kBytesSmall, kBytesLarge, kItemsSmall,
-                             kItemsLarge};
-        for (int q = 0; q < 8; ++q)
-            if (red[0][q]) atomicAdd((unsigned long long*)&acc[slot[q]], (unsigned long long)red[0][q]);
-        if (red[0][8]) atomicMax((unsigned long long*)&acc[kDmaxLarge], (unsigned long long)red[0][8]);
+        part[(int64_t)blockIdx.x * 9 + threadIdx.x] = v;
     }
 }
 
@@ -298,8 +316,24 @@ __global__ void k_heavy_zero(const int32_t* __restrict__ h_dev, uint8_t* __restr
     }
 }
 
-__global__ void k_finish(const int32_t* mp, const int32_t* hp, int64_t* acc) {
-    if (threadIdx.x == 0) {
+// m', h and the classification statistics (sums of the per-block partials;
+// the last one is a maximum).  One wave.
+__global__ void k_finish(const int32_t* mp, const int32_t* hp, const int64_t* __restrict__ part, int32_t nparts,
+                         int64_t* acc) {
+    const int lane = __lane_id();
+    const int slot[9] = {kLightSources, kLightOut, kWedges, kProbes, kBytesSmall, kBytesLarge, kItemsSmall,
+                         kItemsLarge, kDmaxLarge};
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        int64_t v = 0;
+        for (int32_t b = lane; b < nparts; b += 64) {
+            const int64_t x = part[(int64_t)b * 9 + q];
+            v = q == 8 ? (x > v ? x : v) : v + x;
+        }
+        v = q == 8 ? wave_max(v) : wave_sum(v);
+        if (lane == 0) acc[slot[q]] = v;
+    }
+    if (lane == 0) {
         acc[kMp] = mp[0];
         acc[kH] = hp[0];
     }
@@ -914,8 +948,8 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     // 2. orientation by (deg, id): compacted up lists N+(x) and down lists N-(x)
     DevBuf<uint64_t> ubits(NW, s), dbits(NW, s);
     DevBuf<int32_t> upre(NW + 1, s), dpre(NW + 1, s);
-    TC_LAUNCH("orient_bits", k_orient_bits, dim3(grid_for(E2, 256)), dim3(256), 0, s, v_src, v_col, E2, E2_dev,
-              (const uint64_t*)nullptr, degp, ubits.get(), upre.get(), dbits.get(), dpre.get());
+    TC_LAUNCH("orient_bits", k_orient_bits, dim3(grid_for(NW, 16)), dim3(256), 0, s, v_src, v_col, E2, E2_dev, degp,
+              ubits.get(), upre.get(), dbits.get(), dpre.get());
     scan_exclusive_i32(upre.get(), upre.get(), NW, s);
     scan_exclusive_i32(dpre.get(), dpre.get(), NW, s);
     const int32_t* mp_dev = upre.get() + NW;  // number of up entries = m'
@@ -924,8 +958,8 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     positions_at_rows(v_row, n, E2, dbits.get(), dpre.get(), rpD.get(), dminus.get(), s);
     // m' <= m: size the lists by m
     DevBuf<int32_t> colO(g->m, s), srcO(g->m, s), colD(g->m, s), srcD(g->m, s);
-    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), srcO.get(), s);
-    compact_kept(v_col, v_src, E2, dbits.get(), dpre.get(), colD.get(), srcD.get(), s);
+    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), srcO.get(), s, E2_dev);
+    compact_kept(v_col, v_src, E2, dbits.get(), dpre.get(), colD.get(), srcD.get(), s, E2_dev);
 
     // 3. classification, anchor work, item lists
     const int32_t vcap = cfg.vmajor_cap;
@@ -943,10 +977,11 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcD.get(), (const int32_t*)colD.get(),
                   mp_dev, (const int32_t*)code.get(), (const int32_t*)rpO.get(), vcap, 1, Wv.get(), packD.get(), acc);
     DevBuf<int32_t> nsm(n + 1, s), nlg(n + 1, s), nhg(n + 1, s);
-    TC_LAUNCH("classify", k_classify, dim3(std::min<unsigned>(grid_for(n, 256), 2048u)), dim3(256), 0, s, n,
-              (const int32_t*)code.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
-              (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), cfg.small_dmax, nsm.get(), nlg.get(), nhg.get(),
-              acc);
+    const unsigned cgrid = std::min<unsigned>(grid_for(n, 256), kClassifyBlocks);
+    DevBuf<int64_t> cpart((size_t)cgrid * 9, s);
+    TC_LAUNCH("classify", k_classify, dim3(cgrid), dim3(256), 0, s, n, (const int32_t*)code.get(),
+              (const int32_t*)dplus.get(), (const int32_t*)dminus.get(), (const int64_t*)Wu.get(),
+              (const int64_t*)Wv.get(), cfg.small_dmax, nsm.get(), nlg.get(), nhg.get(), cpart.get());
     DevBuf<int32_t> sbase(n + 1, s), lbase(n + 1, s), hbase(n + 1, s), hpos(n + 1, s);
     scan_exclusive_i32(nsm.get(), sbase.get(), n, s);
     scan_exclusive_i32(nlg.get(), lbase.get(), n, s);
@@ -1018,7 +1053,8 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         TC_LAUNCH("heavy_mfma", k_heavy_mfma, dim3((unsigned)mblocks), dim3(256), 0, s, (const uint8_t*)U.get(),
                   (const uint8_t*)UT.get(), h_dev, acc);
     }
-    TC_LAUNCH("finish", k_finish, dim3(1), dim3(64), 0, s, mp_dev, (const int32_t*)hpos.get() + n, acc);
+    TC_LAUNCH("finish", k_finish, dim3(1), dim3(64), 0, s, mp_dev, (const int32_t*)hpos.get() + n,
+              (const int64_t*)cpart.get(), (int32_t)cgrid, acc);
 }
 
 void counts_from_slots(const int64_t* hacc, tc_counts* out) {
@@ -1054,6 +1090,7 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     b += rb(4 * (n + 1)) + rb(4 * n) + 2 * rb(8 * n);                          // heavy, code, Wu, Wv
     b += rb(8 * m) + rb(8 * (cfg.vmajor_cap > 0 ? m : 1));                     // packed descriptors
     b += 7 * rb(4 * (n + 1)) + 4 * scan_scratch_bytes(n);                      // item counts and bases
+    b += rb(8 * 9 * (int64_t)std::min<int64_t>((n + 255) / 256, kClassifyBlocks));  // classification partials
     const int64_t items_max = 2 * n + E2 / kJL + 2;
     b += rb(8 * items_max);
     const LightPlan plan = light_plan(m, maxd, cfg);

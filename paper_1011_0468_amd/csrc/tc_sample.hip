@@ -58,17 +58,44 @@ __global__ void k_rows_at(const int32_t* __restrict__ row_ptr, int64_t n, int64_
     }
 }
 
-__global__ void k_compact(const int32_t* __restrict__ col, const int32_t* __restrict__ src, int64_t E2,
-                          const uint64_t* __restrict__ bits, const int32_t* __restrict__ wpre,
-                          int32_t* __restrict__ col_out, int32_t* __restrict__ src_out) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E2; e += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t w = bits[e >> 6];
-        const int r = (int)(e & 63);
-        if ((w >> r) & 1ull) {
-            const uint64_t below = r == 0 ? 0ull : (w & (~0ull >> (64 - r)));
-            const int32_t p = wpre[e >> 6] + __popcll(below);
-            col_out[p] = col[e];
-            if (src_out) src_out[p] = src[e];
+// Each wave takes 4 words of keep bits (256 entries) per step: the words and
+// their prefixes first, then the kept entries' loads, then the stores, so the
+// latencies of the 4 words overlap.
+__global__ void __launch_bounds__(256) k_compact(const int32_t* __restrict__ col, const int32_t* __restrict__ src,
+                                                  int64_t E2, const int32_t* __restrict__ E2_dev,
+                                                  const uint64_t* __restrict__ bits, const int32_t* __restrict__ wpre,
+                                                  int32_t* __restrict__ col_out, int32_t* __restrict__ src_out) {
+    const int lane = __lane_id();
+    const int64_t valid = E2_dev ? (int64_t)E2_dev[0] : E2;  // entries past it have no bits set
+    const int64_t NW = (valid + 63) / 64;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t w0 = wave * 4; w0 < NW; w0 += nwaves * 4) {
+        uint64_t bw[4];
+        int32_t pre[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool ok = w0 + k < NW;
+            bw[k] = ok ? bits[w0 + k] : 0ull;
+            pre[k] = ok ? wpre[w0 + k] : 0;
+        }
+        int32_t cv[4], sv[4];
+        bool on[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            on[k] = (bw[k] >> lane) & 1ull;  // set bits lie below valid <= E2
+            const int64_t e = (w0 + k) * 64 + lane;
+            cv[k] = on[k] ? col[e] : 0;
+            sv[k] = (on[k] && src_out) ? src[e] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (on[k]) {
+                const int32_t p = pre[k] + __popcll(bw[k] & below);
+                col_out[p] = cv[k];
+                if (src_out) src_out[p] = sv[k];
+            }
         }
     }
 }
@@ -95,10 +122,10 @@ void positions_at_rows(const int32_t* row_ptr, int64_t n, int64_t E2, const uint
 }
 
 void compact_kept(const int32_t* col, const int32_t* src, int64_t E2, const uint64_t* bits, const int32_t* wpre,
-                  int32_t* col_out, int32_t* src_out, hipStream_t s) {
+                  int32_t* col_out, int32_t* src_out, hipStream_t s, const int32_t* E2_dev) {
     if (E2 == 0) return;
-    TC_LAUNCH("compact", k_compact, dim3(grid_for(E2, 256)), dim3(256), 0, s, col, src, E2, bits, wpre, col_out,
-              src_out);
+    TC_LAUNCH("compact", k_compact, dim3(grid_for((E2 + 63) / 64, 16)), dim3(256), 0, s, col, src, E2, E2_dev, bits,
+              wpre, col_out, src_out);
 }
 
 }  // namespace tc
