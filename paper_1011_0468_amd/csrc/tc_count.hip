@@ -347,8 +347,8 @@ __global__ void k_finish(const int32_t* mp, const int32_t* hp, const int64_t* __
 // the high id bits folded in first.  HIP's __umul24 returns a signed int: the
 // product is taken as unsigned before the shift, so the slot is its top lg bits.
 __device__ __forceinline__ uint32_t hslot(int32_t w, int lg) {
-    const uint32_t x = (uint32_t)w ^ ((uint32_t)w >> 21);
-    const uint32_t prod = (uint32_t)__umul24(x, 0x9E3779u);
+    const uint32_t x = (uint32_t)w;
+    const uint32_t prod = (x & 0xFFFFFFu) * 0x9E3779u + (x >> 24);  // v_mad_u32_u24
     return prod >> (32 - lg);
 }
 
@@ -480,12 +480,15 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int32_t g = g0 + lane + 64 * k;
-            x[k] = colO[g < b ? d0 + g : 0];
+            x[k] = *(const int32_t*)((const char*)colO + ((uint32_t)(g < b ? d0 + g : 0) << 2));
         }
     } else {
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            const int j = jlo + 1 + lane + 64 * k;
+            const int jf = jlo + 1 + 64 * k;  // first list of this group of 64 (wave-uniform)
+            if (jf >= nl) break;
+            if (k > 0 && __builtin_amdgcn_readfirstlane(P[jf]) >= g0 + 64 * U) break;  // group starts past it
+            const int j = jf + lane;
             if (j < nl) {
                 const int32_t off = P[j] - g0;  // >= 0: list jlo + 1 starts at g0 or later
                 if (off < 64 * U) mark[off] = 1;
@@ -509,7 +512,7 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int32_t g = g0 + lane + 64 * k;
-            x[k] = colO[g < b ? dk[k] + g : 0];
+            x[k] = *(const int32_t*)((const char*)colO + ((uint32_t)(g < b ? dk[k] + g : 0) << 2));
         }
     }
 #pragma unroll
