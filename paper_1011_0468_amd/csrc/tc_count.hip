@@ -772,7 +772,7 @@ __global__ void __launch_bounds__(256) k_heavy_pack(const int32_t* __restrict__ 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 typedef int32_t v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kHK = 64;          // k-bytes staged per step
+constexpr int kHK = 128;         // k-bytes staged per step
 constexpr int kHRow = kHK + 16;  // LDS row stride: 16-lane groups of 16-byte reads hit 64 distinct banks
 
 // T_H = sum over i < j of (U U)[i][j] U[i][j] with U the strictly upper
@@ -780,15 +780,16 @@ constexpr int kHRow = kHK + 16;  // LDS row stride: 16-lane groups of 16-byte re
 // triangle i < k < j once).  One block per 128 x 128 macro tile (I, J), I <= J,
 // of C = U U; because U is strictly upper triangular, only k in
 // [128 I, 128 J + 128) can contribute, and the k-loop covers exactly those
-// k-blocks.  Per step the block stages 128 rows x 64 k-bytes of U (rows of the
-// tile) and of U^T (columns of the tile) in LDS; each wave owns a 64 x 64
-// quarter as 2 x 2 tiles of v_mfma_i32_32x32x32_i8.  Operand fragments: lane l
-// supplies row (l mod 32) of the A tile and column (l mod 32) of the B tile,
-// 16 consecutive k-bytes starting at 16 (l / 32); A and B use the same
-// k-permutation.  The epilogue masks C with U and adds into T_H.
-// Macro tiles are enumerated column by column (t = J (J + 1) / 2 + I) and
-// dealt to the 8 XCDs in contiguous ranges, so blocks of one XCD share the
-// U^T panels of their columns in that XCD's L2.
+// k-blocks.  Per step the block stages 128 rows x 128 k-bytes of U (rows of
+// the tile) and of U^T (columns of the tile) in LDS while the next step's
+// global loads are in flight in registers; each wave owns a 64 x 64 quarter as
+// 2 x 2 tiles of v_mfma_i32_32x32x32_i8.  Operand fragments: lane l supplies
+// row (l mod 32) of the A tile and column (l mod 32) of the B tile, 16
+// consecutive k-bytes starting at 16 (l / 32); A and B use the same
+// k-permutation.  The epilogue masks C with U and adds into T_H.  Macro tiles
+// are enumerated column by column (t = J (J + 1) / 2 + I) and dealt to the 8
+// XCDs in contiguous ranges, so blocks of one XCD share the U^T panels of
+// their columns in that XCD's L2.
 __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ U, const uint8_t* __restrict__ UT,
                                                      const int32_t* __restrict__ h_dev, int64_t* __restrict__ acc) {
     __shared__ __attribute__((aligned(16))) uint8_t As[kHT * kHRow];
@@ -801,10 +802,9 @@ __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ 
     const int t = threadIdx.x;
     const int w = t >> 6;
     const int lane = __lane_id();
-    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;  // the wave's quarter of the macro tile
-    const int fr = lane & 31, fk = 16 * (lane >> 5);   // fragment row and k offset
-    const int lr = t >> 1, lc = (t & 1) * 32;          // staging: row and byte offset of this thread
-    // XCD-contiguous ranges: block b runs on XCD b mod 8 (gridDim.x is a multiple of 8)
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+    const int fr = lane & 31, fk = 16 * (lane >> 5);
+    const int lr = t >> 1, lc = (t & 1) * (kHK / 2);   // staging: row and byte offset of this thread
     const int64_t xcd = blockIdx.x & 7;
     const int64_t per_xcd = gridDim.x >> 3;
     const int64_t chunk = (ntiles + 7) / 8;
@@ -823,17 +823,28 @@ __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ 
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) c[i][j] = (v16i){0};
-        for (int64_t k0 = row0; k0 < col0 + kHT; k0 += kHK) {
-            const v4i a0 = *(const v4i*)(ga + k0);
-            const v4i a1 = *(const v4i*)(ga + k0 + 16);
-            const v4i b0 = *(const v4i*)(gb + k0);
-            const v4i b1 = *(const v4i*)(gb + k0 + 16);
+        const int64_t kend = col0 + kHT;
+        v4i ra[4], rb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ra[q] = *(const v4i*)(ga + row0 + 16 * q);
+            rb[q] = *(const v4i*)(gb + row0 + 16 * q);
+        }
+        for (int64_t k0 = row0; k0 < kend; k0 += kHK) {
             __syncthreads();  // the previous step's fragment reads are done
-            *(v4i*)(As + lr * kHRow + lc) = a0;
-            *(v4i*)(As + lr * kHRow + lc + 16) = a1;
-            *(v4i*)(Bs + lr * kHRow + lc) = b0;
-            *(v4i*)(Bs + lr * kHRow + lc + 16) = b1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                *(v4i*)(As + lr * kHRow + lc + 16 * q) = ra[q];
+                *(v4i*)(Bs + lr * kHRow + lc + 16 * q) = rb[q];
+            }
             __syncthreads();
+            if (k0 + kHK < kend) {  // block-uniform: the next step's loads fly during these MFMAs
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    ra[q] = *(const v4i*)(ga + k0 + kHK + 16 * q);
+                    rb[q] = *(const v4i*)(gb + k0 + kHK + 16 * q);
+                }
+            }
 #pragma unroll
             for (int ks = 0; ks < kHK; ks += 32) {
                 v4i af[2], bf[2];
@@ -848,16 +859,15 @@ __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ 
                         c[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[i], bf[j], c[i][j], 0, 0, 0);
             }
         }
-        // accumulator element q of lane l: row 8 (q / 4) + 4 (l / 32) + q mod 4, column l mod 32
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const int64_t colj = col0 + wc + 32 * j + fr;
+                const uint8_t* ucol = U + col0 + wc + 32 * j + fr;
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int64_t row = row0 + wr + 32 * i + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    total += (int64_t)c[i][j][q] * (int64_t)U[row * hp + colj];
+                    total += (int64_t)c[i][j][q] * (int64_t)ucol[row * hp];
                 }
             }
     }
