@@ -136,8 +136,9 @@ tc_status tc_estimate(tc_graph g, double p, const uint64_t* seeds, int32_t num_s
    mix64(mix64((l >> 6) << 32 | i) ^ mix64(seed ^ 0x52505F5452414345)) is 0, else -1;
    q[l] = x_l^T A^3 x_l computed exactly in int64, and *tri_est = (sum_l q[l]
    summed in 128-bit) / (6k).  q is a host array of k entries; tri_est may be
-   NULL.  TC_ERR_OVERFLOW if k * sum over directed edges (i,j) of deg_i * deg_j
-   could reach 2^63. */
+   NULL.  TC_ERR_OVERFLOW, before any sweep, if k * sum over directed edges
+   (i,j) of deg_i * deg_j reaches 2^62 (q_l and their sum could then leave
+   int64). */
 tc_status tc_rp_trace(tc_graph g, int32_t k, uint64_t seed, void* stream, int64_t* q, double* tri_est);
 
 /* ---- autotuner ------------------------------------------------------------ */

@@ -19,6 +19,8 @@
 #include "tc_internal.h"
 #include "tc_device.h"
 
+#include <vector>
+
 namespace tc {
 
 namespace {
@@ -49,30 +51,26 @@ __global__ void __launch_bounds__(256) k_rp_spmm(int64_t E2, const int32_t* __re
     int32_t cur = __builtin_amdgcn_readfirstlane(src[e0]);
     int32_t cnt = 0, ones = 0;
     for (int64_t eb = e0; eb < e1; eb += 64) {
-        // 64 entries per coalesced load; entry k of the batch is read from lane k
+        // 64 entries per coalesced load and their 64 sign words in one vector
+        // gather: entry k of the batch and its word are read from lane k
         const int64_t el = eb + lane;
         const int32_t vi = el < e1 ? src[el] : -1;
         const int32_t vj = el < e1 ? col[el] : 0;
-        for (int k0 = 0; k0 < 64; k0 += kRpUnroll) {
-            int32_t ii[kRpUnroll];
-            uint64_t ww[kRpUnroll];
-#pragma unroll
-            for (int k = 0; k < kRpUnroll; ++k) {
-                ii[k] = __builtin_amdgcn_readlane(vi, k0 + k);
-                ww[k] = ii[k] >= 0 ? words[__builtin_amdgcn_readlane(vj, k0 + k)] : 0ull;
+        const uint64_t wv = words[vj];
+        const uint32_t wlo = (uint32_t)wv, whi = (uint32_t)(wv >> 32);
+        const int kn = (int)(e1 - eb < 64 ? e1 - eb : 64);  // wave-uniform
+        for (int k = 0; k < kn; ++k) {
+            const int32_t i = __builtin_amdgcn_readlane(vi, k);
+            if (i != cur) {
+                rp_flush(cur, cnt, ones, e0, e1, row_ptr, Y, lane);
+                cur = i;
+                cnt = 0;
+                ones = 0;
             }
-#pragma unroll
-            for (int k = 0; k < kRpUnroll; ++k) {
-                if (ii[k] < 0) break;  // wave-uniform: past the range end
-                if (ii[k] != cur) {
-                    rp_flush(cur, cnt, ones, e0, e1, row_ptr, Y, lane);
-                    cur = ii[k];
-                    cnt = 0;
-                    ones = 0;
-                }
-                ++cnt;
-                ones += (int32_t)((ww[k] >> lane) & 1ull);
-            }
+            ++cnt;
+            const uint32_t lo = __builtin_amdgcn_readlane(wlo, k);
+            const uint32_t hi = __builtin_amdgcn_readlane(whi, k);
+            ones += (int32_t)(((lane < 32 ? lo : hi) >> (lane & 31)) & 1u);
         }
     }
     rp_flush(cur, cnt, ones, e0, e1, row_ptr, Y, lane);
@@ -129,14 +127,19 @@ __global__ void __launch_bounds__(256) k_rp_dot(int64_t E2, const int32_t* __res
     }
 }
 
-// sum over directed edges (i, j) of deg_i * deg_j, in double (a bound only)
-__global__ void k_rp_bound(const int32_t* __restrict__ src, const int32_t* __restrict__ col,
-                           const int32_t* __restrict__ deg, int64_t E2, double* __restrict__ out) {
+// sum over directed edges (i, j) of deg_i * deg_j, in double (a bound only):
+// one partial per block, summed on the host
+__global__ void __launch_bounds__(256) k_rp_bound(const int32_t* __restrict__ src, const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ deg, int64_t E2,
+                                                   double* __restrict__ part) {
     double s = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E2; e += (int64_t)gridDim.x * blockDim.x)
         s += (double)deg[src[e]] * (double)deg[col[e]];
     s = wave_sum(s);
-    if (__lane_id() == 0) atomicAdd(out, s);
+    __shared__ double red[4];
+    if (__lane_id() == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 }  // namespace
@@ -146,16 +149,19 @@ void rp_trace(const tc_graph_s* g, int32_t k, uint64_t seed, hipStream_t s, int6
     for (int32_t l = 0; l < k; ++l) q_host[l] = 0;
     if (n == 0 || E2 == 0) return;
     {
-        DevBuf<double> bound(1, s);
-        fill_i64(reinterpret_cast<int64_t*>(bound.get()), 0, 1, s);  // +0.0
+        // |q_l| <= sum over entries (i, j) of |Y_il| |Y_jl| <= sum of deg_i deg_j; every q_l and their sum
+        // stay exact while k times that is below 2^62 (margin for the double rounding)
         unsigned blocks = ceil_div(E2, 256);
-        if (blocks > 8192) blocks = 8192;
+        if (blocks > 1024) blocks = 1024;
+        DevBuf<double> part(blocks, s);
         TC_LAUNCH("rp_bound", k_rp_bound, dim3(blocks), dim3(256), 0, s, (const int32_t*)g->src,
-                  (const int32_t*)g->col, (const int32_t*)g->deg, E2, bound.get());
-        double hb = 0.0;
-        check_hip(hipMemcpyAsync(&hb, bound.get(), sizeof(double), hipMemcpyDeviceToHost, s), "bound");
+                  (const int32_t*)g->col, (const int32_t*)g->deg, E2, part.get());
+        std::vector<double> hpart(blocks);
+        check_hip(hipMemcpyAsync(hpart.data(), part.get(), sizeof(double) * blocks, hipMemcpyDeviceToHost, s),
+                  "bound");
         check_hip(hipStreamSynchronize(s), "sync");
-        // |q_l| <= sum_(i,j) deg_i deg_j; keep k times that below 2^62 (margin for the double rounding)
+        double hb = 0.0;
+        for (double v : hpart) hb += v;
         if (hb * (double)k >= 4.611686018427387904e18)
             fail(TC_ERR_OVERFLOW, "k * sum deg_i deg_j reaches 2^62: q could overflow int64");
     }

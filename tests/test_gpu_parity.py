@@ -156,6 +156,24 @@ def test_rp_matches_oracle(gpu):
         assert est == oest
 
 
+def test_rp_star_bound_and_overflow(gpu):
+    # star K_{1,N}: sum over CSR entries of deg_i deg_j = 2 N^2; k * 2^33 >= 2^62
+    # must be refused before any q is returned, a small k must match the oracle
+    # (the row of the centre spans many 4096-entry sweep ranges)
+    N = 65536
+    src = np.zeros(N, np.int32)
+    dst = np.arange(1, N + 1, dtype=np.int32)
+    g = _build(gpu, (N + 1, src, dst))
+    with pytest.raises(gpu.TcError) as e:
+        gpu.tc_rp_trace(g, 1 << 30, 0)
+    assert "overflow" in str(e.value).lower() or "2^62" in str(e.value)
+    og = oracle.normalise(N + 1, src, dst)
+    q, est = gpu.tc_rp_trace(g, 70, 9)
+    oq, oest = oracle.rp_trace(og, 70, 9)
+    assert np.array_equal(q, oq)
+    assert est == oest
+
+
 def test_invalid_p_and_groups(gpu):
     g = _build(gpu, special.complete(5))
     for p in (0.0, -0.1, 1.5, float("nan"), float("inf")):
