@@ -21,6 +21,8 @@
 #include "tc_internal.h"
 #include "tc_device.h"
 
+#include <atomic>
+
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -529,7 +531,7 @@ __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D
                                               int32_t* mark, int lane) {
     int32_t cnt = 0;
     if (a >= b) return 0;
-    int jlo = find_list(P, nl, a);
+    int jlo = a == 0 ? 0 : find_list(P, nl, a);  // P[0] = 0 owns position 0
     int32_t xa[U], xb[U];
     uint64_t va[U], vb[U];
     gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, xa, va);
@@ -569,10 +571,9 @@ __device__ __forceinline__ void build_hash(int32_t rs, int32_t d, const int32_t*
 // (start in colO minus P, so position g of list j reads colO[D[j] + g]).
 // Returns nl; *total receives the number of positions.
 template <int NT>
-__device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32_t cnt, int32_t* P, int32_t* D,
-                                               int32_t* red, int t, int32_t* total) {
+__device__ __forceinline__ void load_lists(const int2* __restrict__ L, int32_t cnt, int t,
+                                           int32_t (&st)[(kJL + NT - 1) / NT], int32_t (&ln)[(kJL + NT - 1) / NT]) {
     constexpr int R = (kJL + NT - 1) / NT;
-    int32_t st[R], ln[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int j = t * R + k;  // consecutive entries per thread
@@ -580,6 +581,13 @@ __device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32
         st[k] = e.x;
         ln[k] = e.y;
     }
+}
+
+template <int NT>
+__device__ __forceinline__ int32_t stage_loaded(const int32_t (&st)[(kJL + NT - 1) / NT],
+                                                const int32_t (&ln)[(kJL + NT - 1) / NT], int32_t* P, int32_t* D,
+                                                int32_t* red, int t, int32_t* total) {
+    constexpr int R = (kJL + NT - 1) / NT;
     int32_t loc = 0, nloc = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -613,9 +621,21 @@ __device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32
     return ntot;
 }
 
+template <int NT>
+__device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32_t cnt, int32_t* P, int32_t* D,
+                                               int32_t* red, int t, int32_t* total) {
+    constexpr int R = (kJL + NT - 1) / NT;
+    int32_t st[R], ln[R];
+    load_lists<NT>(L, cnt, t, st, ln);
+    return stage_loaded<NT>(st, ln, P, D, red, t, total);
+}
+
 // One wave per item, persistent over items with a static stride.  Item
 // (x, r): anchor x, kind u (x >= 0) or v (encoded ~x), entries r*kJL.. of the
-// iterated list.  LDS per wave: hash (4*DS slots), P (kJL+1), D (kJL), flags (64 kU).
+// iterated list.  LDS per wave: hash (4*DS slots), P (kJL+1), D (kJL), flags
+// (64 kU).  Items are short, so the chain of dependent loads that opens an
+// item (item, row offsets, keys and list descriptors) is issued for the next
+// item while the current one closes.
 template <int DS>
 __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ items,
                                                       const int32_t* __restrict__ n_items_dev,
@@ -624,6 +644,8 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
                                                       const int2* __restrict__ packD, int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 4 * DS;                                     // buckets of 4 slots, load <= 1/4
     constexpr int ROW = (HS_MAX + 2 * kJL + 1 + 64 * kU + 3) / 4 * 4;  // keeps every row 16-byte aligned
+    constexpr int KR = (DS + 63) / 64;                                 // keys per lane
+    constexpr int LR = (kJL + 63) / 64;                                // list descriptors per lane
     __shared__ __attribute__((aligned(16))) int32_t lds[4][ROW];
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
@@ -636,30 +658,60 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
     const int64_t n_items = n_items_dev[0];
-    int64_t total = 0;
-    for (int64_t it = gw; it < n_items; it += nw) {
+    // the opening of item `it`: anchor row (rs, d) and its iterated list (L, cnt)
+    auto header = [&](int64_t it, int32_t& rs, int32_t& d, const int2*& L, int32_t& cnt) {
         const int2 item = items[it];
         const bool kind_u = item.x >= 0;
         const int32_t x = kind_u ? item.x : ~item.x;
-        const int32_t rs = rpO[x];
-        const int32_t d = rpO[x + 1] - rs;
-        const int2* L;
+        rs = rpO[x];
+        d = rpO[x + 1] - rs;
         int32_t llen;
         if (kind_u) { L = packU + rs; llen = d; }
         else { const int32_t ds = rpD[x]; L = packD + ds; llen = rpD[x + 1] - ds; }
         const int32_t j0 = item.y * kJL;
-        const int32_t cnt = min(kJL, llen - j0);
-        const int lg = bucket_bits(d);
-        const int hs = 4 << lg;
-        for (int i = lane; i < hs; i += 64) tab[i] = -1;
-        if (lane == 0) P[0] = 0;
-        wave_lds_sync();
-        build_hash<64>(rs, d, colO, tab, lg, lane);
-        int32_t W;
-        const int32_t nl = stage_lists<64>(L + j0, cnt, P, D, nullptr, lane, &W);
-        wave_lds_sync();
-        total += close_flat<kU, false>(P, D, nl, 0, W, colO, tab, lg, mark, lane);  // wave-uniform
-        wave_lds_sync();
+        L += j0;
+        cnt = min(kJL, llen - j0);
+    };
+    auto body = [&](int32_t rs, int32_t d, const int2* L, int32_t cnt, int32_t (&kv)[KR], int32_t (&st)[LR],
+                    int32_t (&ln)[LR]) {
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int j = lane + 64 * k;
+            kv[k] = j < d ? colO[rs + j] : -1;
+        }
+        load_lists<64>(L, cnt, lane, st, ln);
+    };
+    int64_t total = 0;
+    if (gw < n_items) {
+        int32_t rs, d, cnt;
+        const int2* L;
+        int32_t kv[KR], st[LR], ln[LR];
+        header(gw, rs, d, L, cnt);
+        body(rs, d, L, cnt, kv, st, ln);
+        for (int64_t it = gw; it < n_items; it += nw) {
+            const bool more = it + nw < n_items;  // wave-uniform
+            int32_t rs2 = 0, d2 = 0, cnt2 = 0;
+            const int2* L2 = L;
+            if (more) header(it + nw, rs2, d2, L2, cnt2);
+            const int lg = bucket_bits(d);
+            const int hs = 4 << lg;
+            for (int i = lane; i < hs; i += 64) tab[i] = -1;
+            if (lane == 0) P[0] = 0;
+            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < KR; ++k)
+                if (kv[k] >= 0) hash_insert(tab, lg, kv[k]);
+            int32_t W;
+            const int32_t nl = stage_loaded<64>(st, ln, P, D, nullptr, lane, &W);
+            wave_lds_sync();
+            if (more) body(rs2, d2, L2, cnt2, kv, st, ln);  // in flight during the closure
+            total += close_flat<kU, false>(P, D, nl, 0, W, colO, tab, lg, mark, lane);  // wave-uniform
+            wave_lds_sync();
+            rs = rs2;
+            d = d2;
+            L = L2;
+            cnt = cnt2;
+        }
     }
     if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTL], (unsigned long long)total);
 }
@@ -1009,7 +1061,16 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)nsm.get(),
                   (const int32_t*)sbase.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
                   (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
-        const int64_t blocks = (int64_t)num_cus() * cfg.light_blocks_per_cu;
+        // a persistent grid larger than what stays resident would run its last
+        // blocks in a second round: cap the blocks per CU at the resident count
+        static const int resident = [] {
+            int r = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_light_small<128>, 256, 0) != hipSuccess || r < 1)
+                r = 1;
+            (void)hipGetLastError();
+            return r;
+        }();
+        const int64_t blocks = (int64_t)num_cus() * std::min<int32_t>(cfg.light_blocks_per_cu, resident);
         TC_LAUNCH("light_small", k_light_small<128>, dim3((unsigned)blocks), dim3(256), 0, s,
                   (const int2*)items.get(), (const int32_t*)sbase.get() + n, (const int32_t*)rpO.get(),
                   (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const int2*)packU.get(),
@@ -1024,10 +1085,19 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         const size_t per_block = (size_t)large_block_words(dcap);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
         if (!global) {
-            // resident blocks per CU: 160 KB of LDS per CU on gfx950, at most 8 blocks of 4 waves
-            int64_t per_cu = (int64_t)((160 * 1024) / (lds_bytes + 64));
-            if (per_cu > 8) per_cu = 8;
-            if (per_cu < 1) per_cu = 1;
+            // one round of resident blocks (LDS and registers permitting, at most 8 per CU)
+            static std::atomic<int> resident[16];  // by log2(dcap); every thread computes the same value
+            int lgc = 0;
+            while ((1 << lgc) < dcap) ++lgc;
+            int r = resident[lgc].load(std::memory_order_relaxed);
+            if (!r) {
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_light_large<false>, 256, lds_bytes) !=
+                        hipSuccess || r < 1)
+                    r = 1;
+                (void)hipGetLastError();
+                resident[lgc].store(r, std::memory_order_relaxed);
+            }
+            const int64_t per_cu = std::min(r, 8);
             const int64_t blocks = (int64_t)num_cus() * per_cu;
             TC_LAUNCH("light_large", k_light_large<false>, dim3((unsigned)blocks), dim3(256), lds_bytes, s,
                       (const int2*)items.get(), (const int32_t*)base.get() + n, (const int32_t*)rpO.get(),
