@@ -134,17 +134,22 @@ __device__ __forceinline__ bool vmajor(int32_t du, int32_t dv, int32_t vcap) {
     return du <= dv && dv <= vcap;
 }
 
-// per vertex: heavy flag and code = d+(x) if x is a light source (light, d+ >= 2), else 0
+// per vertex: heavy flag, code = d+(x) if x is a light source (light, d+ >= 2)
+// else 0, and rowD[x] = (start of N+(x), code ? d+ : ~d+), which gives both
+// the list and the code with one 8-byte load
 __global__ void k_vertex_prep(int64_t n, const int32_t* __restrict__ degp, const int32_t* __restrict__ dplus,
-                              const int32_t* __restrict__ mp_dev, int32_t ha, int32_t hb, int32_t* __restrict__ heavy,
-                              int32_t* __restrict__ code) {
+                              const int32_t* __restrict__ rpO, const int32_t* __restrict__ mp_dev, int32_t ha,
+                              int32_t hb, int32_t* __restrict__ heavy, int32_t* __restrict__ code,
+                              int2* __restrict__ rowD) {
     const int64_t mp = mp_dev[0];
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t dg = degp[x];
         const bool hv = dg > 0 && is_heavy(dg, mp, ha, hb);
         heavy[x] = hv ? 1 : 0;
         const int32_t dp = dplus[x];
-        code[x] = (!hv && dp >= 2) ? dp : 0;
+        const bool src = !hv && dp >= 2;
+        code[x] = src ? dp : 0;
+        rowD[x] = make_int2(rpO[x], src ? dp : ~dp);
     }
 }
 
@@ -177,10 +182,9 @@ __device__ __forceinline__ bool run_tail_sum(int32_t key, bool valid, int64_t va
 // (0, 0) if the pair is closed from the other side.  The closure kernels then
 // stage an anchor's lists with coalesced reads instead of gathers.
 __global__ void __launch_bounds__(256) k_work(const int32_t* __restrict__ rowE, const int32_t* __restrict__ colE,
-                                               const int32_t* __restrict__ mp_dev, const int32_t* __restrict__ code,
-                                               const int32_t* __restrict__ rpO, int32_t vcap, int32_t down,
-                                               int64_t* __restrict__ W, int2* __restrict__ pack,
-                                               int64_t* __restrict__ acc) {
+                                               const int32_t* __restrict__ mp_dev, const int2* __restrict__ rowD,
+                                               int32_t vcap, int32_t down, int64_t* __restrict__ W,
+                                               int2* __restrict__ pack, int64_t* __restrict__ acc) {
     const int64_t mo = mp_dev[0];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t gsum = 0;
@@ -194,19 +198,22 @@ __global__ void __launch_bounds__(256) k_work(const int32_t* __restrict__ rowE, 
             const int32_t y = colE[e];
             int2 pk = make_int2(0, 0);
             if (!down) {
-                const int32_t cu = code[key];
-                if (cu > 0) {
-                    const int32_t sv = rpO[y];
-                    const int32_t dv = rpO[y + 1] - sv;
+                const int32_t ck = rowD[key].y;
+                if (ck > 0) {  // key is a light source, ck = d+(key)
+                    const int2 ry = rowD[y];
+                    const int32_t dv = ry.y >= 0 ? ry.y : ~ry.y;
                     gsum += dv;
-                    if (!vmajor(cu, dv, vcap)) { valid = true; val = dv; pk = make_int2(sv, dv); }
+                    if (!vmajor(ck, dv, vcap)) { valid = true; val = dv; pk = make_int2(ry.x, dv); }
                 }
             } else {
-                const int32_t cu = code[y];
-                if (cu > 0 && vmajor(cu, rpO[key + 1] - rpO[key], vcap)) {
-                    valid = true;
-                    val = cu;
-                    pk = make_int2(rpO[y], cu);
+                const int2 ry = rowD[y];
+                if (ry.y > 0) {  // y is a light source, ry.y = d+(y)
+                    const int32_t ck = rowD[key].y;
+                    if (vmajor(ry.y, ck >= 0 ? ck : ~ck, vcap)) {
+                        valid = true;
+                        val = ry.y;
+                        pk = make_int2(ry.x, ry.y);
+                    }
                 }
             }
             pack[e] = pk;
@@ -1029,18 +1036,20 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     // 3. classification, anchor work, item lists
     const int32_t vcap = cfg.vmajor_cap;
     DevBuf<int32_t> heavy(n + 1, s), code(n, s);
+    DevBuf<int2> rowD(n, s);
     TC_LAUNCH("vertex_prep", k_vertex_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, n, degp,
-              (const int32_t*)dplus.get(), mp_dev, cfg.heavy_num, cfg.heavy_den, heavy.get(), code.get());
+              (const int32_t*)dplus.get(), (const int32_t*)rpO.get(), mp_dev, cfg.heavy_num, cfg.heavy_den,
+              heavy.get(), code.get(), rowD.get());
     DevBuf<int64_t> Wu(n, s), Wv(n, s);
     fill_i64(Wu.get(), 0, n, s);
     fill_i64(Wv.get(), 0, n, s);
     const unsigned wgrid = std::min<unsigned>(grid_for(g->m, 256), 8192u);
     DevBuf<int2> packU(g->m, s), packD(vcap > 0 ? g->m : 1, s);
     TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcO.get(), (const int32_t*)colO.get(),
-              mp_dev, (const int32_t*)code.get(), (const int32_t*)rpO.get(), vcap, 0, Wu.get(), packU.get(), acc);
+              mp_dev, (const int2*)rowD.get(), vcap, 0, Wu.get(), packU.get(), acc);
     if (vcap > 0)
         TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcD.get(), (const int32_t*)colD.get(),
-                  mp_dev, (const int32_t*)code.get(), (const int32_t*)rpO.get(), vcap, 1, Wv.get(), packD.get(), acc);
+                  mp_dev, (const int2*)rowD.get(), vcap, 1, Wv.get(), packD.get(), acc);
     DevBuf<int32_t> nsm(n + 1, s), nlg(n + 1, s), nhg(n + 1, s);
     const unsigned cgrid = std::min<unsigned>(grid_for(n, 256), kClassifyBlocks);
     DevBuf<int64_t> cpart((size_t)cgrid * 9, s);
@@ -1170,7 +1179,7 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     b += 2 * rb(8 * NW) + 2 * rb(4 * (NW + 1)) + 2 * scan_scratch_bytes(NW);  // orientation bits, prefixes
     b += 2 * rb(4 * (n + 1)) + 2 * rb(4 * n);                                 // rpO, d+, rpD, d-
     b += 4 * rb(4 * m);                                                        // up and down lists
-    b += rb(4 * (n + 1)) + rb(4 * n) + 2 * rb(8 * n);                          // heavy, code, Wu, Wv
+    b += rb(4 * (n + 1)) + rb(4 * n) + rb(8 * n) + 2 * rb(8 * n);              // heavy, code, rowD, Wu, Wv
     b += rb(8 * m) + rb(8 * (cfg.vmajor_cap > 0 ? m : 1));                     // packed descriptors
     b += 7 * rb(4 * (n + 1)) + 4 * scan_scratch_bytes(n);                      // item counts and bases
     b += rb(8 * 9 * (int64_t)std::min<int64_t>((n + 255) / 256, kClassifyBlocks));  // classification partials
