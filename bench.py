@@ -11,6 +11,10 @@ int8-MFMA block, rescale).  The metric is sampled-graph edges per second: the
 edges of the four counted graphs (m, m'_0.5, m'_0.1, m'_0.05) divided by the
 step time.  The CSR build is timed separately (the paper also leaves the
 conversion to its sorted-list format out of its timings, section 4.2).
+Before timing, the autotuner picks per operating point the launch parameters
+and the heavy multiplier c (light iff deg <= c sqrt(m'), c in {1/4, 1/2, 1,
+2}) on a different sample (seed + 1); the count is the same for every c.
+--defaults times the paper's split (c = 1) with default launch parameters.
 
 Prints one JSON line.  Only one GPU is supported.
 """
@@ -283,8 +287,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0)
     ap.add_argument("--requests", type=int, default=1000, help="serving workload: number of requests")
-    ap.add_argument("--autotune", action="store_true",
-                    help="search launch parameters per operating point before timing (default: library defaults)")
+    ap.add_argument("--defaults", action="store_true",
+                    help="use the library defaults (heavy iff deg > sqrt(m'), default launch parameters) instead of "
+                         "the autotuner's choice per operating point")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -323,11 +328,11 @@ def main():
     del src, dst
     info = g.info()
 
-    tuned = args.autotune
+    tuned = not args.defaults
     tunings = {}
     for p in ps:
-        if tuned:  # untimed: pick launch parameters per operating point; the threshold stays deg <= sqrt(m')
-            tunings[str(p)] = tc.tc_autotune(g, p, seed=args.seed, search_heavy=False)
+        if tuned:  # untimed, on another sample (seed + 1): launch parameters and heavy multiplier per point
+            tunings[str(p)] = tc.tc_autotune(g, p, seed=args.seed + 1, search_heavy=True)
         else:
             tunings[str(p)] = tc.tc_tune_get(g, p)
 
@@ -403,7 +408,9 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": info["n"], "m": info["m"], "ps": ps, "seed": args.seed,
-                   "split": "light iff deg <= sqrt(m')", "csr": "int32, resident in HBM"},
+                   "split": ("light iff deg <= c sqrt(m'), c = heavy_num/heavy_den per point from the autotuner"
+                             if tuned else "light iff deg <= sqrt(m')"),
+                   "csr": "int32, resident in HBM"},
         "roofline": roofline,
         "csr_build_ms": round(csr_ms, 2),
         "per_call_ms": dict(zip([str(p) for p in ps], per_call_ms)),

@@ -44,8 +44,8 @@ CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, u
                      hipStream_t s) {
     CountConfig cur;
     tune_lookup(g, sampled, p, &cur);
-    int32_t heavy[3][2] = {{1, 2}, {1, 1}, {2, 1}};
-    int nh = 3;
+    int32_t heavy[4][2] = {{1, 4}, {1, 2}, {1, 1}, {2, 1}};
+    int nh = 4;
     if (!search_heavy) {
         heavy[0][0] = cur.heavy_num;
         heavy[0][1] = cur.heavy_den;
@@ -66,7 +66,12 @@ CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, u
                 c.vmajor_cap = cap;
                 c.small_dmax = dm;
                 tc_counts r;
-                count_core(g, sampled, thr, salt, c, s, &r);  // warm-up (allocations, caches)
+                try {
+                    count_core(g, sampled, thr, salt, c, s, &r);  // warm-up (allocations, caches)
+                } catch (const Error& e) {
+                    if (e.status == TC_ERR_OVERFLOW) continue;  // heavy block bound too large for this split
+                    throw;
+                }
                 const auto t0 = std::chrono::steady_clock::now();
                 count_core(g, sampled, thr, salt, c, s, &r);
                 const double ms =
@@ -78,6 +83,7 @@ CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, u
                     best = c;
                 }
             }
+    if (T < 0) fail(TC_ERR_OVERFLOW, "autotune: no candidate fits the heavy block bound");
     tune_store(g, sampled, p, best);
     return best;
 }
