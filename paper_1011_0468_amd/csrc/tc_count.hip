@@ -785,29 +785,42 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
 // heavy block
 // ---------------------------------------------------------------------------
 
-// rank of each heavy vertex in (deg, id) order, by counting smaller keys
+// rank of each heavy vertex in (deg, id) order, by counting smaller keys: block
+// (bx, by) compares heavy vertices bx*256.. with the kRankChunk keys by*kRankChunk..
+// and adds its counts into rank[] (zeroed beforehand)
+constexpr int kRankChunk = 1024;
+
 __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev,
-                                                     const int32_t* __restrict__ degp, int32_t* __restrict__ hidx,
-                                                     int32_t* __restrict__ horder) {
+                                                     const int32_t* __restrict__ degp, int32_t* __restrict__ rank) {
     __shared__ int32_t kd[256], kx[256];
     const int32_t h = h_dev[0];
-    if ((int64_t)blockIdx.x * 256 >= h) return;  // block-uniform
+    const int64_t j0 = (int64_t)blockIdx.y * kRankChunk;
+    if ((int64_t)blockIdx.x * 256 >= h || j0 >= h) return;  // block-uniform
     const int i = blockIdx.x * 256 + threadIdx.x;
     int32_t x = -1, dx = 0;
     if (i < h) { x = hlist[i]; dx = degp[x]; }
+    const int64_t j1 = min((int64_t)h, j0 + kRankChunk);
     int32_t r = 0;
-    for (int j0 = 0; j0 < h; j0 += 256) {
-        const int j = j0 + threadIdx.x;
-        if (j < h) { kx[threadIdx.x] = hlist[j]; kd[threadIdx.x] = degp[kx[threadIdx.x]]; }
+    for (int64_t jb = j0; jb < j1; jb += 256) {
+        const int64_t j = jb + threadIdx.x;
+        if (j < j1) { kx[threadIdx.x] = hlist[j]; kd[threadIdx.x] = degp[kx[threadIdx.x]]; }
         __syncthreads();
-        const int lim = min(256, h - j0);
+        const int lim = (int)min((int64_t)256, j1 - jb);
         if (i < h)
             for (int q = 0; q < lim; ++q) r += rank_below(kd[q], kx[q], dx, x) ? 1 : 0;
         __syncthreads();
     }
-    if (i < h) {
-        hidx[x] = r;
-        horder[r] = x;
+    if (i < h && r) atomicAdd(&rank[i], r);
+}
+
+__global__ void k_heavy_place(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev,
+                              const int32_t* __restrict__ rank, int32_t* __restrict__ hidx,
+                              int32_t* __restrict__ horder) {
+    const int32_t h = h_dev[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < h; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = hlist[i];
+        hidx[x] = rank[i];
+        horder[rank[i]] = x;
     }
 }
 
@@ -1131,8 +1144,12 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         const int32_t* h_dev = hpos.get() + n;
         TC_LAUNCH("heavy_list", k_heavy_list, dim3(grid_for(n, 256)), dim3(256), 0, s, n,
                   (const int32_t*)heavy.get(), (const int32_t*)hpos.get(), hlist.get());
-        TC_LAUNCH("heavy_rank", k_heavy_rank, dim3(ceil_div(hmax, 256)), dim3(256), 0, s, (const int32_t*)hlist.get(),
-                  h_dev, degp, hidx.get(), horder.get());
+        DevBuf<int32_t> hrank(hmax, s);
+        fill_i32(hrank.get(), 0, hmax, s);
+        TC_LAUNCH("heavy_rank", k_heavy_rank, dim3(ceil_div(hmax, 256), ceil_div(hmax, kRankChunk)), dim3(256), 0, s,
+                  (const int32_t*)hlist.get(), h_dev, degp, hrank.get());
+        TC_LAUNCH("heavy_place", k_heavy_place, dim3(ceil_div(hmax, 256)), dim3(256), 0, s,
+                  (const int32_t*)hlist.get(), h_dev, (const int32_t*)hrank.get(), hidx.get(), horder.get());
         DevBuf<uint8_t> U((size_t)hp_max * hp_max, s), UT((size_t)hp_max * hp_max, s);
         TC_LAUNCH("heavy_zero", k_heavy_zero, dim3(2048), dim3(256), 0, s, h_dev, U.get(), UT.get());
         TC_LAUNCH("heavy_pack", k_heavy_pack, dim3((unsigned)hmax), dim3(256), 0, s, (const int32_t*)horder.get(),
@@ -1191,7 +1208,7 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     const int64_t hmax = heavy_bound(n, m, cfg.heavy_num, cfg.heavy_den);
     if (hmax >= 3) {
         const int64_t hp = heavy_pad(hmax);
-        b += 2 * rb(4 * hmax) + rb(4 * n) + 2 * rb(hp * hp);
+        b += 3 * rb(4 * hmax) + rb(4 * n) + 2 * rb(hp * hp);  // list, order, rank, index, U, UT
     }
     return b;
 }
