@@ -47,9 +47,9 @@ def _source_sha():
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel, workload):
+def _traffic(kernel, workload, tunings):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source."""
+    taken on the current kernel source with the same launch parameters."""
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
@@ -57,7 +57,7 @@ def _traffic(kernel, workload):
         rec = json.load(open(path))
     except Exception:
         return None
-    if rec.get("source_sha") != _source_sha():
+    if rec.get("source_sha") != _source_sha() or rec.get("tunings") != tunings:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -287,6 +287,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0)
     ap.add_argument("--requests", type=int, default=1000, help="serving workload: number of requests")
+    ap.add_argument("--tunings", default=None,
+                    help="JSON object p -> tuning (the bench line's own 'tunings'): use these instead of autotuning")
     ap.add_argument("--defaults", action="store_true",
                     help="use the library defaults (heavy iff deg > sqrt(m'), default launch parameters) instead of "
                          "the autotuner's choice per operating point")
@@ -329,9 +331,15 @@ def main():
     info = g.info()
 
     tuned = not args.defaults
+    given = json.loads(args.tunings) if args.tunings else None
     tunings = {}
     for p in ps:
-        if tuned:  # untimed, on another sample (seed + 1): launch parameters and heavy multiplier per point
+        if tuned and given is not None:  # a previous run's choice (profiling runs reuse it)
+            t = given[str(p)]
+            tc.tc_tune_set(g, p, heavy=(t["heavy_num"], t["heavy_den"]), small_dmax=t["small_dmax"],
+                           vmajor_cap=t["vmajor_cap"], blocks_per_cu=t["blocks_per_cu"])
+            tunings[str(p)] = tc.tc_tune_get(g, p)
+        elif tuned:  # untimed, on another sample (seed + 1): launch parameters and heavy multiplier per point
             tunings[str(p)] = tc.tc_autotune(g, p, seed=args.seed + 1, search_heavy=True)
         else:
             tunings[str(p)] = tc.tc_tune_get(g, p)
@@ -388,7 +396,7 @@ def main():
     dom = max(DOMINANT, key=lambda k: kern[k][0])
     ms_tot, launches, model = kern[dom]
     achieved = (model / (ms_tot / 1e3)) / 1e9 if ms_tot > 0 else 0.0
-    traffic = _traffic(dom, args.workload)
+    traffic = _traffic(dom, args.workload, tunings)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "avg_launch_ms": round(ms_tot / max(launches, 1), 4), "launches": launches,

@@ -162,8 +162,10 @@ tc_status tc_tune_get(tc_graph g, double p, tc_tuning* t);
 /* Time every candidate of a fixed grid (vmajor_cap in {0, 1024},
    small_dmax in {64, 128}, and, if search_heavy, the heavy multiplier c =
    heavy_num/heavy_den in {1/4, 1/2, 1, 2}; else the multiplier of the stored
-   entry or 1) on the graph sampled with (p, seed), store the fastest and
-   return it in *best (may be NULL).  Candidates whose heavy block bound
+   entry or 1) on the graph sampled with (p, seed) (best of two runs each),
+   store the fastest and return it in *best (may be NULL).  Candidates within
+   3% of the fastest are ties, resolved towards the defaults (c = 1, then
+   vmajor_cap 1024, then small_dmax 128).  Candidates whose heavy block bound
    exceeds its limit (TC_ERR_OVERFLOW) are skipped.  Counts of all candidates
    must agree; TC_ERR_DEVICE otherwise. */
 tc_status tc_autotune(tc_graph g, double p, uint64_t seed, int32_t search_heavy, void* stream, tc_tuning* best);

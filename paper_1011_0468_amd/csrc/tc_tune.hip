@@ -4,10 +4,12 @@
 // the tuner checks that every candidate returns the same T.
 #include "tc_internal.h"
 
+#include <algorithm>
 #include <chrono>
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 namespace tc {
 
@@ -53,8 +55,15 @@ CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, u
     }
     const int32_t caps[2] = {0, 1024};
     const int32_t dmaxs[2] = {64, 128};
-    CountConfig best;
-    double best_ms = 1e300;
+    // candidates within 3% of the fastest count as ties; a tie goes to the
+    // candidate closest to the defaults (c = 1, vmajor_cap 1024, small_dmax 128),
+    // so the choice does not flip with timing noise
+    auto distance = [&](const CountConfig& c) {
+        const CountConfig d;
+        return (c.heavy_num * d.heavy_den != d.heavy_num * c.heavy_den ? 4 : 0) + (c.vmajor_cap != d.vmajor_cap ? 2 : 0) +
+               (c.small_dmax != d.small_dmax ? 1 : 0);
+    };
+    std::vector<std::pair<double, CountConfig>> timed;
     int64_t T = -1;
     for (int hi = 0; hi < nh; ++hi)
         for (int32_t cap : caps)
@@ -72,17 +81,33 @@ CountConfig autotune(const tc_graph_s* g, int sampled, double p, uint64_t thr, u
                     if (e.status == TC_ERR_OVERFLOW) continue;  // heavy block bound too large for this split
                     throw;
                 }
-                const auto t0 = std::chrono::steady_clock::now();
-                count_core(g, sampled, thr, salt, c, s, &r);
-                const double ms =
-                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                double ms = 1e300;
+                for (int rep = 0; rep < 2; ++rep) {  // best of two
+                    const auto t0 = std::chrono::steady_clock::now();
+                    count_core(g, sampled, thr, salt, c, s, &r);
+                    ms = std::min(ms, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                                          .count());
+                }
                 if (T >= 0 && r.triangles != T) fail(TC_ERR_DEVICE, "autotune: candidates disagree on the count");
                 T = r.triangles;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = c;
-                }
+                timed.emplace_back(ms, c);
             }
+    CountConfig best;
+    if (!timed.empty()) {
+        double fastest = 1e300;
+        for (auto& tcand : timed) fastest = std::min(fastest, tcand.first);
+        int best_dist = 1 << 30;
+        double best_ms = 1e300;
+        for (auto& tcand : timed) {
+            if (tcand.first > fastest * 1.03) continue;
+            const int dist = distance(tcand.second);
+            if (dist < best_dist || (dist == best_dist && tcand.first < best_ms)) {
+                best_dist = dist;
+                best_ms = tcand.first;
+                best = tcand.second;
+            }
+        }
+    }
     if (T < 0) fail(TC_ERR_OVERFLOW, "autotune: no candidate fits the heavy block bound");
     tune_store(g, sampled, p, best);
     return best;
