@@ -1,7 +1,8 @@
 // Exact triangle count of a (possibly sparsified) graph with the light/heavy
 // vertex partition of section 3.2.
 //
-//   1. degrees of the counted graph (after the section 3.1 coin, if sampled);
+//   1. the counted graph: the input CSR, or the entries kept by the section
+//      3.1 coin compacted into a CSR of their own, and its degrees;
 //   2. orientation u -> v iff (deg u, u) < (deg v, v); every triangle is
 //      charged to its lowest-ranked vertex.  Heavy vertices (deg > c m^(1/2))
 //      rank above every light vertex, so a triangle whose lowest vertex is
@@ -13,7 +14,7 @@
 //      lists through an LDS hash set of the other: pairs whose N+(u) is
 //      shorter are grouped by v (N+(v) staged once, the N+(u) of v's light
 //      in-neighbours streamed), the others by u;
-//   4. heavy phase: the <= 2 m^(1/2) heavy vertices, in rank order, form a
+//   4. heavy phase: the < 2 m^(1/2) / c heavy vertices, in rank order, form a
 //      strictly upper-triangular 0/1 matrix U; sum((U U) .* U) counts each
 //      all-heavy triangle once (the matrix-multiplication route of Alon,
 //      Yuster and Zwick that section 2.1 and section 3 build on) and runs on
