@@ -153,6 +153,19 @@ def serve(args):
                       file=sys.stderr, flush=True)
     pairs = int(sum(len(r[1]) for r in reqs))
     budget = 8 << 30
+    pinned = not args.pageable
+    if pinned:
+        # request payloads in page-locked host memory, as a serving front end
+        # would keep them: the copies to the device then run at DMA speed
+        import torch
+        keep = []
+        for i, (n, s, d) in enumerate(reqs):
+            ps_ = torch.empty(len(s), dtype=torch.int32, pin_memory=True)
+            pd_ = torch.empty(len(d), dtype=torch.int32, pin_memory=True)
+            ps_.numpy()[:] = s
+            pd_.numpy()[:] = d
+            keep.append((ps_, pd_))
+            reqs[i] = (n, ps_.numpy(), pd_.numpy())
 
     def run(lanes, arrivals):
         with tc.Server(budget, lanes=lanes) as sv:
@@ -192,7 +205,7 @@ def serve(args):
                       "fifo_p99_ms": head["fifo"]["p99_ms"], "capacity_req_per_s": {"fifo": mu1,
                                                                                   "lanes4": closed4["req_per_s"]},
                       "closed_loop": {"fifo": closed1, "lanes4": closed4}, "loads": loads,
-                      "identical_alone_and_in_mix": True,
+                      "identical_alone_and_in_mix": True, "host_payloads": "pinned" if pinned else "pageable",
                       "config": {"workload": "serve", "requests": N, "pairs": pairs, "scales": [10, 20],
                                  "ps": list(synth.SERVE_P), "budget_bytes": budget, "arrival_seed": 12345}}),
           flush=True)
@@ -287,6 +300,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0)
     ap.add_argument("--requests", type=int, default=1000, help="serving workload: number of requests")
+    ap.add_argument("--pageable", action="store_true",
+                    help="serving workload: keep request payloads in pageable host memory")
     ap.add_argument("--tunings", default=None,
                     help="JSON object p -> tuning (the bench line's own 'tunings'): use these instead of autotuning")
     ap.add_argument("--defaults", action="store_true",
