@@ -15,6 +15,7 @@ constexpr int kRsItems = 16;
 constexpr int kRsTile = kRsThreads * kRsItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+static_assert(kRadix == kRsThreads, "one thread per digit in the scatter's scan");
 
 // Emit (u,v) and (v,u) packed as u << nb | v; self-loops become the sentinel
 // (all 2nb bits set), which sorts after every valid key.
@@ -53,28 +54,34 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const K* __restrict__ ke
     for (int d = threadIdx.x; d < kRadix; d += kRsThreads) hist[(int64_t)d * gridDim.x + blockIdx.x] = cnt[d];
 }
 
-// Stable scatter: keys of the tile are ranked in index order (iteration,
-// wave, lane); peers with the same digit inside a wave are found by 8 ballots.
+// Stable scatter of one tile of kRsTile keys.  All 16 keys of a thread are
+// loaded first; within each wave and iteration, peers with the same digit are
+// found by 8 ballots; the per-(iteration, wave) digit counts go to LDS and one
+// scan per digit over the 64 (iteration, wave) groups, in index order, gives
+// every group its output base: two block barriers per tile.
 template <typename K>
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K* __restrict__ in, K* __restrict__ out,
                                                             int64_t N, int shift,
                                                             const int32_t* __restrict__ offs) {
     constexpr int NW = kRsThreads / 64;
-    __shared__ int32_t run[kRadix];
-    __shared__ int32_t wcnt[NW][kRadix];
-    __shared__ int32_t wbase[NW][kRadix];
-    const int w = threadIdx.x >> 6;
-    for (int d = threadIdx.x; d < kRadix; d += kRsThreads) {
-        run[d] = offs[(int64_t)d * gridDim.x + blockIdx.x];
-        for (int j = 0; j < NW; ++j) wcnt[j][d] = 0;
-    }
-    __syncthreads();
+    constexpr int NG = kRsItems * NW;  // (iteration, wave) groups in index order
+    __shared__ int32_t cnt[NG][kRadix];
+    const int t = threadIdx.x;
+    const int w = t >> 6;
+    for (int g = 0; g < NG; ++g) cnt[g][t] = 0;  // kRadix == kRsThreads
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    K key[kRsItems];
+    int32_t dg[kRsItems], rk[kRsItems];
+#pragma unroll
     for (int i = 0; i < kRsItems; ++i) {
-        const int64_t idx = base + (int64_t)i * kRsThreads + threadIdx.x;
-        const bool valid = idx < N;
-        const K key = valid ? in[idx] : (K)0;
-        const int d = (int)((key >> shift) & (kRadix - 1));
+        const int64_t idx = base + (int64_t)i * kRsThreads + t;
+        key[i] = idx < N ? in[idx] : (K)0;
+    }
+    __syncthreads();  // counters zeroed
+#pragma unroll
+    for (int i = 0; i < kRsItems; ++i) {
+        const bool valid = base + (int64_t)i * kRsThreads + t < N;
+        const int d = (int)((key[i] >> shift) & (kRadix - 1));
         uint64_t peers = ballot64(valid);
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
@@ -82,22 +89,24 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K* __restrict__
             const uint64_t bal = ballot64(valid && bit);
             peers &= bit ? bal : ~bal;
         }
-        const int rank = __popcll(peers & lanes_below());
-        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
-        __syncthreads();
-        for (int dd = threadIdx.x; dd < kRadix; dd += kRsThreads) {
-            int acc = run[dd];
-            for (int j = 0; j < NW; ++j) {
-                const int c = wcnt[j][dd];
-                wbase[j][dd] = acc;
-                acc += c;
-                wcnt[j][dd] = 0;
-            }
-            run[dd] = acc;
-        }
-        __syncthreads();
-        if (valid) out[wbase[w][d] + rank] = key;
+        const int r = __popcll(peers & lanes_below());
+        if (valid && r == 0) cnt[i * NW + w][d] = __popcll(peers);
+        dg[i] = d;
+        rk[i] = valid ? r : -1;
     }
+    __syncthreads();
+    {
+        int32_t run = offs[(int64_t)t * gridDim.x + blockIdx.x];  // digit t of this tile
+        for (int g = 0; g < NG; ++g) {
+            const int32_t c = cnt[g][t];
+            cnt[g][t] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRsItems; ++i)
+        if (rk[i] >= 0) out[cnt[i * NW + w][dg[i]] + rk[i]] = key[i];
 }
 
 template <typename K>
