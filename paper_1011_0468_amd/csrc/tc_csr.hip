@@ -6,6 +6,8 @@
 #include "tc_internal.h"
 #include "tc_device.h"
 
+#include <algorithm>
+
 namespace tc {
 
 namespace {
@@ -119,36 +121,49 @@ __global__ void k_unique_flags(const K* __restrict__ keys, int64_t N, K sentinel
 
 // Write unique keys to col/src and count degrees: unique keys of one wave form
 // runs of equal rows (keys are sorted); each run adds its length with one atomic.
+// Each wave takes 4 chunks of 64 keys per step with all their loads (keys, the
+// key before each, positions) issued before the first use.
 template <typename K>
-__global__ void k_unique_scatter(const K* __restrict__ keys, int64_t N, K sentinel, int nb,
-                                 const int32_t* __restrict__ pos, int32_t* __restrict__ col,
-                                 int32_t* __restrict__ srcrow, int32_t* __restrict__ deg) {
+__global__ void __launch_bounds__(256) k_unique_scatter(const K* __restrict__ keys, int64_t N, K sentinel, int nb,
+                                                         const int32_t* __restrict__ pos, int32_t* __restrict__ col,
+                                                         int32_t* __restrict__ srcrow, int32_t* __restrict__ deg) {
     const K vmask = ((K)1 << nb) - 1;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int lane = __lane_id();
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < N; i0 += stride) {
-        const int64_t i = i0 + threadIdx.x;
-        bool uniq = false;
-        int32_t u = -1;
-        if (i < N) {
-            const K k = keys[i];
-            uniq = k != sentinel && (i == 0 || keys[i - 1] != k);
-            if (uniq) {
-                u = (int32_t)(k >> nb);
-                const int32_t p = pos[i];
-                col[p] = (int32_t)(k & vmask);
-                srcrow[p] = u;
-            }
+    const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t c0 = wave * 256; c0 < N; c0 += nwaves * 256) {
+        K k[4], kp[4];
+        int32_t ps[4];
+        bool in[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = c0 + 64 * q + lane;
+            in[q] = i < N;
+            const int64_t ic = in[q] ? i : N - 1;
+            k[q] = keys[ic];
+            kp[q] = ic > 0 ? keys[ic - 1] : sentinel;
+            ps[q] = pos[ic];
         }
-        const uint64_t active = ballot64(uniq);
-        const int32_t up = __shfl_up(u, 1, 64);
-        const bool prev_same = lane > 0 && ((active >> (lane - 1)) & 1ull) && up == u;
-        const bool head = uniq && !prev_same;
-        const uint64_t heads = ballot64(head);
-        if (head) {
-            const uint64_t breaks = (heads | ~active) & (lane == 63 ? 0ull : (~0ull << (lane + 1)));
-            const int next = breaks ? __builtin_ctzll(breaks) : 64;
-            atomicAdd(&deg[u], next - lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = c0 + 64 * q + lane;
+            const bool uniq = in[q] && k[q] != sentinel && (i == 0 || kp[q] != k[q]);
+            int32_t u = -1;
+            if (uniq) {
+                u = (int32_t)(k[q] >> nb);
+                col[ps[q]] = (int32_t)(k[q] & vmask);
+                srcrow[ps[q]] = u;
+            }
+            const uint64_t active = ballot64(uniq);
+            const int32_t up = __shfl_up(u, 1, 64);
+            const bool prev_same = lane > 0 && ((active >> (lane - 1)) & 1ull) && up == u;
+            const bool head = uniq && !prev_same;
+            const uint64_t heads = ballot64(head);
+            if (head) {
+                const uint64_t breaks = (heads | ~active) & (lane == 63 ? 0ull : (~0ull << (lane + 1)));
+                const int next = breaks ? __builtin_ctzll(breaks) : 64;
+                atomicAdd(&deg[u], next - lane);
+            }
         }
     }
 }
@@ -203,8 +218,9 @@ int build_csr_t(int64_t n, int64_t P, const int32_t* src, const int32_t* dst, in
     g->deg = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s);
     g->home = s;
     fill_i32(g->deg, 0, n, s);
-    TC_LAUNCH("csr_unique_scatter", k_unique_scatter<K>, dim3(blocks), dim3(256), 0, s, ka.get(), N, sentinel, nb,
-              (const int32_t*)pos.get(), g->col, g->src, g->deg);
+    TC_LAUNCH("csr_unique_scatter", k_unique_scatter<K>, dim3(std::max<unsigned>(1, (unsigned)std::min<int64_t>(
+                                                                 (N + 1023) / 1024, 65536))),
+              dim3(256), 0, s, ka.get(), N, sentinel, nb, (const int32_t*)pos.get(), g->col, g->src, g->deg);
     scan_exclusive_i32(g->deg, g->row_ptr, n, s);
     return 0;
 }
