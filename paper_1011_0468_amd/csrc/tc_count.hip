@@ -532,14 +532,28 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D
 // Closure tests for positions [a, b) of the concatenated streamed lists
 // (layout as in gather_strips); returns the wave's number of hits.  Software-pipelined with two register sets:
 // the gathers of the next super-strip are issued, unconditionally, before the
-// hash probes of the current one, and no register copy waits on them.
-template <int U, bool GLOBAL>
+// hash probes of the current one, and no register copy waits on them.  SHORT
+// adds unpipelined paths for ranges of at most one super-strip (worth it where
+// most ranges are that short; elsewhere the extra code costs occupancy).
+template <int U, bool GLOBAL, bool SHORT>
 __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D, int nl, int32_t a, int32_t b,
                                               const int32_t* __restrict__ colO, const int32_t* tab, int lg,
                                               int32_t* mark, int lane) {
     int32_t cnt = 0;
     if (a >= b) return 0;
     int jlo = a == 0 ? 0 : find_list(P, nl, a);  // P[0] = 0 owns position 0
+    if (SHORT && b - a <= 64) {  // one strip
+        int32_t x1[1];
+        uint64_t v1[1];
+        gather_strips<1, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, x1, v1);
+        return probe_many<1>(tab, lg, x1, v1);
+    }
+    if (SHORT && b - a <= 64 * U) {  // one super-strip
+        int32_t x1[U];
+        uint64_t v1[U];
+        gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, x1, v1);
+        return probe_many<U>(tab, lg, x1, v1);
+    }
     int32_t xa[U], xb[U];
     uint64_t va[U], vb[U];
     gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, xa, va);
@@ -713,7 +727,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
             const int32_t nl = stage_loaded<64>(st, ln, P, D, nullptr, lane, &W);
             wave_lds_sync();
             if (more) body(rs2, d2, L2, cnt2, kv, st, ln);  // in flight during the closure
-            total += close_flat<kU, false>(P, D, nl, 0, W, colO, tab, lg, mark, lane);  // wave-uniform
+            total += close_flat<kU, false, true>(P, D, nl, 0, W, colO, tab, lg, mark, lane);  // wave-uniform
             wave_lds_sync();
             rs = rs2;
             d = d2;
@@ -776,7 +790,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         const int32_t q = (W + 3) / 4;
         const int32_t a = min(w * q, W);
         const int32_t b = min(a + q, W);
-        total += close_flat<kU, GLOBAL>(P, D, nl, a, b, colO, tab, lg, mark, lane);  // wave-uniform
+        total += close_flat<kU, GLOBAL, false>(P, D, nl, a, b, colO, tab, lg, mark, lane);  // wave-uniform
         __syncthreads();
     }
     if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTL], (unsigned long long)total);
