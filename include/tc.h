@@ -75,8 +75,10 @@ typedef struct {
     int64_t wedges;           /* sum of C(d+(u), 2) over those u */
     int64_t gather;           /* sum over those pairs of d+(v) (list entries read if every pair
                                  streamed N+(v)) */
-    int64_t probes;           /* list entries actually streamed and tested (each pair streams the
-                                 shorter of N+(u), N+(v), within the staging cap) */
+    int64_t probes;           /* list entries actually streamed and tested: pair (u, v) streams
+                                 the members of N+(u) ranked above v (all of N+(u) when
+                                 d+(u) > 1024) or N+(v), the shorter within the staging cap,
+                                 and nothing when no member of N+(u) ranks above v */
     int64_t items_small;      /* work items of the wave-per-item kernel */
     int64_t items_large;      /* work items of the block-per-item kernel */
     int64_t model_bytes_small;/* bytes the wave-per-item kernel must read (list model) */
@@ -148,8 +150,9 @@ tc_status tc_rp_trace(tc_graph g, int32_t k, uint64_t seed, void* stream, int64_
 typedef struct {
     int32_t heavy_num, heavy_den; /* heavy iff heavy_den^2 deg^2 > heavy_num^2 m */
     int32_t small_dmax;           /* anchors with out-degree <= this use one wave per item (1..128) */
-    int32_t vmajor_cap;           /* pairs (u,v) with d+(u) <= d+(v) <= cap are closed from v's side;
-                                     0 closes every pair from u's side */
+    int32_t vmajor_cap;           /* pairs (u,v) whose streamed part of N+(u) is no longer than
+                                     d+(v), with d+(v) <= cap, are closed from v's side; 0 closes
+                                     every pair from u's side */
     int32_t blocks_per_cu;        /* persistent grid of the wave-per-item kernel (1..16) */
 } tc_tuning;
 

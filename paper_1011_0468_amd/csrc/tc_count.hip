@@ -10,10 +10,12 @@
 //   3. light phase: for every light u, the wedges of section 3.2 (pairs of
 //      out-neighbours) are closed by counting, for each v in N+(u), the
 //      common members of N+(u) and N+(v).  Only the third edge of a wedge
-//      needs a test (section 4.2); the test streams the shorter of the two
-//      lists through an LDS hash set of the other: pairs whose N+(u) is
-//      shorter are grouped by v (N+(v) staged once, the N+(u) of v's light
-//      in-neighbours streamed), the others by u;
+//      needs a test (section 4.2).  N+(u) is first sorted into rank order,
+//      so that only its members ranked above v can close (u, v); the test
+//      streams that part of N+(u), or N+(v), whichever is shorter, through an
+//      LDS hash set of the other list: pairs of the first kind are grouped by
+//      v (N+(v) staged once, the parts of its light in-neighbours' lists
+//      streamed), the others by u;
 //   4. heavy phase: the < 2 m^(1/2) / c heavy vertices, in rank order, form a
 //      strictly upper-triangular 0/1 matrix U; sum((U U) .* U) counts each
 //      all-heavy triangle once (the matrix-multiplication route of Alon,
@@ -58,19 +60,17 @@ constexpr int kU = 4;
 // orientation
 // ---------------------------------------------------------------------------
 
-// Per CSR entry (u, v) of a kept edge: "up" if (deg u, u) < (deg v, v), else
-// "down".  Each kept undirected edge has exactly one up entry (in the row of
-// its lower-ranked end) and one down entry (in the row of its higher end).
-// E2 bounds the buffers; E2_dev (if not null) holds the number of valid
-// entries, which may be smaller (a compacted sample in buffers sized for the
-// full graph): words past it get zero bits.  Each wave takes 4 words (256
-// entries) per step and issues all their loads before the first use, the
-// degree gathers likewise.
+// Per CSR entry (u, v) of a kept edge: "up" if (deg u, u) < (deg v, v).  Each
+// kept undirected edge has exactly one up entry, in the row of its
+// lower-ranked end.  E2 bounds the buffers; E2_dev (if not null) holds the
+// number of valid entries, which may be smaller (a compacted sample in buffers
+// sized for the full graph): words past it get zero bits.  Each wave takes 4
+// words (256 entries) per step and issues all their loads before the first
+// use, the degree gathers likewise.
 __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__ src, const int32_t* __restrict__ col,
                                                       int64_t E2, const int32_t* __restrict__ E2_dev,
                                                       const int32_t* __restrict__ degp, uint64_t* __restrict__ ubits,
-                                                      int32_t* __restrict__ ucnt, uint64_t* __restrict__ dbits,
-                                                      int32_t* __restrict__ dcnt) {
+                                                      int32_t* __restrict__ ucnt) {
     const int lane = __lane_id();
     const int64_t NW = (E2 + 63) / 64;
     const int64_t valid = E2_dev ? (int64_t)E2_dev[0] : E2;
@@ -98,14 +98,10 @@ __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const bool up = in[k] && rank_below(du[k], u[k], dv[k], v[k]);
-            const bool dn = in[k] && !up;
             const uint64_t bu = ballot64(up);
-            const uint64_t bd = ballot64(dn);
             if (lane == k && w0 + k < NW) {
                 ubits[w0 + k] = bu;
                 ucnt[w0 + k] = __popcll(bu);
-                dbits[w0 + k] = bd;
-                dcnt[w0 + k] = __popcll(bd);
             }
         }
     }
@@ -128,125 +124,282 @@ __device__ __forceinline__ bool is_heavy(int64_t deg, int64_t m, int32_t a, int3
     return (int64_t)b * b * deg * deg > (int64_t)a * a * m;
 }
 
-// Pair (u, v), u light: closed from v's side ("v-major": stage N+(v), stream
-// N+(u)) when N+(u) is the shorter list and N+(v) fits the staging cap; else
-// from u's side (stage N+(u), stream N+(v)).
-__device__ __forceinline__ bool vmajor(int32_t du, int32_t dv, int32_t vcap) {
-    return du <= dv && dv <= vcap;
+// Orders one wave's shared-table writes before its later reads.  LDS
+// operations of a wave complete in order, so for tables in LDS only the
+// compiler must be kept from moving accesses across (fences) and outstanding
+// LDS results are drained (lgkmcnt); global loads stay in flight.  Tables in
+// global scratch (GLOBAL) need every outstanding access drained.
+template <bool GLOBAL>
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (GLOBAL) __builtin_amdgcn_s_waitcnt(0);
+    else __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt unrestricted
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void wave_lds_sync() { wave_sync<false>(); }
+
+// Pair (u, v), u a light source, whose test streams len entries of N+(u)
+// (the members of N+(u) ranked above v, or all of N+(u)) or the d+(v) entries
+// of N+(v): closed from v's side ("v-major": stage N+(v), stream the part of
+// N+(u)) when that part is the shorter list and N+(v) fits the staging cap;
+// else from u's side (stage N+(u), stream N+(v)).
+__device__ __forceinline__ bool vmajor(int32_t len, int32_t dv, int32_t vcap) {
+    return len <= dv && dv <= vcap;
 }
 
 // per vertex: heavy flag, code = d+(x) if x is a light source (light, d+ >= 2)
-// else 0, and rowD[x] = (start of N+(x), code ? d+ : ~d+), which gives both
-// the list and the code with one 8-byte load
+// else 0, and d-(x) = deg - d+ (the in-degree of the orientation)
 __global__ void k_vertex_prep(int64_t n, const int32_t* __restrict__ degp, const int32_t* __restrict__ dplus,
-                              const int32_t* __restrict__ rpO, const int32_t* __restrict__ mp_dev, int32_t ha,
-                              int32_t hb, int32_t* __restrict__ heavy, int32_t* __restrict__ code,
-                              int2* __restrict__ rowD) {
+                              const int32_t* __restrict__ mp_dev, int32_t ha, int32_t hb, int32_t* __restrict__ heavy,
+                              int32_t* __restrict__ code, int32_t* __restrict__ dminus) {
     const int64_t mp = mp_dev[0];
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t dg = degp[x];
         const bool hv = dg > 0 && is_heavy(dg, mp, ha, hb);
         heavy[x] = hv ? 1 : 0;
         const int32_t dp = dplus[x];
-        const bool src = !hv && dp >= 2;
-        code[x] = src ? dp : 0;
-        rowD[x] = make_int2(rpO[x], src ? dp : ~dp);
+        code[x] = !hv && dp >= 2 ? dp : 0;
+        dminus[x] = dg - dp;
     }
 }
 
-// Sum of `val` over the run of equal `key` that ends at this lane; true on the
-// run's last lane.  All lanes of the wave must call it; invalid lanes pass val 0.
-__device__ __forceinline__ bool run_tail_sum(int32_t key, bool valid, int64_t val, int64_t* sum) {
-    const int lane = __lane_id();
-    const int64_t incl = wave_inclusive_sum(val);
-    const int32_t pk = __shfl_up(key, 1, 64);
-    const int32_t nk = __shfl_down(key, 1, 64);
-    const uint64_t active = ballot64(valid);
-    const bool head = valid && !(lane > 0 && ((active >> (lane - 1)) & 1ull) && pk == key);
-    const bool tail = valid && !(lane < 63 && ((active >> (lane + 1)) & 1ull) && nk == key);
-    const uint64_t heads = ballot64(head);
-    const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-    const uint64_t hm = heads & le;
-    const int my_head = hm ? 63 - __builtin_clzll(hm) : 0;
-    const int src_lane = my_head > 0 ? my_head - 1 : 0;
-    const int64_t before = __shfl(incl, src_lane, 64);
-    *sum = incl - (my_head > 0 ? before : 0);
-    return tail;
+// rowQ[x] = (start of N+(x), code ? d+ : ~d+, deg, start of x's v-major
+// descriptors): everything the anchor work needs of a vertex in one 16-byte load
+__global__ void k_row_q(int64_t n, const int32_t* __restrict__ rpO, const int32_t* __restrict__ code,
+                        const int32_t* __restrict__ dplus, const int32_t* __restrict__ degp,
+                        const int32_t* __restrict__ rpD, int4* __restrict__ rowQ) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = code[x];
+        rowQ[x] = make_int4(rpO[x], c ? c : ~dplus[x], degp[x], rpD[x]);
+    }
 }
 
-// Work of the anchors.  Over up entries (u -> v, grouped by u):
-//   Wu[u] += d+(v) for u-major pairs; gather statistic += d+(v) for every pair.
-// Over down entries (row v, entry u, grouped by v):
-//   Wv[v] += d+(u) for v-major pairs.
-// Every entry also receives, at its own position in `pack`, the list the
-// closure kernels stream for it: (start of N+(y) in the up lists, length), or
-// (0, 0) if the pair is closed from the other side.  The closure kernels then
-// stage an anchor's lists with coalesced reads instead of gathers.
-__global__ void __launch_bounds__(256) k_work(const int32_t* __restrict__ rowE, const int32_t* __restrict__ colE,
-                                               const int32_t* __restrict__ mp_dev, const int2* __restrict__ rowD,
-                                               int32_t vcap, int32_t down, int64_t* __restrict__ W,
-                                               int2* __restrict__ pack, int64_t* __restrict__ acc) {
-    const int64_t mo = mp_dev[0];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// Longest out-list that the anchor work sorts into rank order (one wave, in
+// LDS).  A longer list keeps CSR order and each of its pairs streams all of it.
+constexpr int kSortCap = 1024;
+
+// The rank (deg, id) as one unsigned integer: rank_below(du, u, dv, v) iff
+// rank_key(du, u) < rank_key(dv, v).
+__device__ __forceinline__ uint64_t rank_key(int32_t deg, int32_t w) {
+    return ((uint64_t)(uint32_t)deg << 32) | (uint32_t)w;
+}
+
+// One pair (u, v) of the anchor work: v is entry k of N+(u) (rs = start of
+// N+(u), d = d+(u)), qv = rowQ[v].  If N+(u) is in rank order, only its
+// entries after k can close (u, v) (a common out-neighbour w of u and v ranks
+// above v); a pair with none is skipped.  The pair's descriptor goes to
+// packU[rs + k] (u-major: (start of N+(v), d+(v)); else (0, 0)) or, v-major,
+// to the next free slot of v's descriptors (start and length of the streamed
+// part of N+(u)).  cw[v] accumulates (count << 32) + total length of v's
+// descriptors with one atomic: lengths sum to at most m' < 2^31.
+__device__ __forceinline__ void pair_work(int32_t rs, int32_t d, int32_t k, int32_t v, int4 qv, bool sorted,
+                                          int32_t vcap, int2* __restrict__ packU, int2* __restrict__ packD,
+                                          unsigned long long* __restrict__ cw, int64_t& wu, int64_t& gsum) {
+    const int32_t dv = qv.y >= 0 ? qv.y : ~qv.y;
+    gsum += dv;
+    const int32_t len = sorted ? d - 1 - k : d;
+    int2 pk = make_int2(0, 0);
+    if (len > 0) {
+        if (vmajor(len, dv, vcap)) {
+            const unsigned long long old = atomicAdd(&cw[v], (1ull << 32) | (uint32_t)len);
+            packD[qv.w + (int32_t)(old >> 32)] = make_int2(sorted ? rs + k + 1 : rs, len);
+        } else {
+            pk = make_int2(qv.x, dv);
+            wu += dv;
+        }
+    }
+    packU[rs + k] = pk;
+}
+
+// lane ^ J exchange (J a power of two below 64)
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+    if constexpr (J < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (J << 10) | 0x1F);
+    else return (uint32_t)__shfl_xor((int)v, J, 64);
+}
+
+// Merge steps J, J/2, .., 1 of the bitonic network's stage K over lanes
+// (key, idx pairs; runs of K lanes alternate ascending and descending).
+template <int K, int J>
+__device__ __forceinline__ void bitonic_steps(uint64_t& key, int32_t& idx, int lane) {
+    if constexpr (J > 0) {
+        const uint64_t ok = ((uint64_t)lane_xor<J>((uint32_t)(key >> 32)) << 32) | lane_xor<J>((uint32_t)key);
+        const int32_t oi = (int32_t)lane_xor<J>((uint32_t)idx);
+        const bool keep_min = ((lane & K) == 0) == ((lane & J) == 0);
+        if (keep_min ? ok < key : ok > key) {
+            key = ok;
+            idx = oi;
+        }
+        bitonic_steps<K, J / 2>(key, idx, lane);
+    }
+}
+
+// Ascending sort of the keys of lanes [0, G) (G a power of two <= 64), each
+// carrying idx along.  Lanes at or past G take part in runs of their own.
+template <int G, int K = 2>
+__device__ __forceinline__ void bitonic_lanes(uint64_t& key, int32_t& idx, int lane) {
+    bitonic_steps<K, K / 2>(key, idx, lane);
+    if constexpr (K < G) bitonic_lanes<G, 2 * K>(key, idx, lane);
+}
+
+// Block reduction of the gather statistic into acc (256 threads).
+__device__ __forceinline__ void add_gather(int64_t gsum, int64_t* acc) {
+    gsum = wave_sum(gsum);
+    __shared__ int64_t red[4];
+    if (__lane_id() == 0) red[threadIdx.x >> 6] = gsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t t = red[0] + red[1] + red[2] + red[3];
+        if (t) atomicAdd((unsigned long long*)&acc[kGather], (unsigned long long)t);
+    }
+}
+
+// Anchor work of the light sources with d+ <= 64, one wave per list: N+(u) is
+// sorted into rank order in registers and written back, and each of its pairs
+// gets its descriptor (pair_work).  Each wave takes 64 consecutive vertices
+// per step and writes Wu (the length u-major pairs stream) of all of them, 0
+// for the lists left to k_work_lds.
+__global__ void __launch_bounds__(256) k_work_lanes(int64_t n, const int4* __restrict__ rowQ,
+                                                     int32_t* __restrict__ colO, int32_t vcap,
+                                                     int2* __restrict__ packU, int2* __restrict__ packD,
+                                                     unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
+                                                     int64_t* __restrict__ acc) {
+    const int lane = __lane_id();
+    const int64_t gw = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * 4;
     int64_t gsum = 0;
-    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < mo; e0 += stride) {
-        const int64_t e = e0 + threadIdx.x;
-        bool valid = false;
-        int32_t key = -1;
-        int64_t val = 0;
-        if (e < mo) {
-            key = rowE[e];
-            const int32_t y = colE[e];
-            int2 pk = make_int2(0, 0);
-            if (!down) {
-                const int32_t ck = rowD[key].y;
-                if (ck > 0) {  // key is a light source, ck = d+(key)
-                    const int2 ry = rowD[y];
-                    const int32_t dv = ry.y >= 0 ? ry.y : ~ry.y;
-                    gsum += dv;
-                    if (!vmajor(ck, dv, vcap)) { valid = true; val = dv; pk = make_int2(ry.x, dv); }
+    for (int64_t x0 = gw * 64; x0 < n; x0 += nw * 64) {
+        const int64_t x = x0 + lane;
+        const int4 q = x < n ? rowQ[x] : make_int4(0, 0, 0, 0);
+        int64_t mine = 0;
+        uint64_t todo = ballot64(q.y >= 2 && q.y <= 64);
+        while (todo) {
+            const int l = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int32_t rs = __builtin_amdgcn_readlane(q.x, l);
+            const int32_t d = __builtin_amdgcn_readlane(q.y, l);
+            const bool in = lane < d;
+            const int32_t w = in ? colO[rs + lane] : 0;
+            const int4 qw = in ? rowQ[w] : make_int4(0, 0, 0, 0);
+            uint64_t key = in ? rank_key(qw.z, w) : ~0ull;
+            int32_t idx = lane;
+            if (d <= 4) bitonic_lanes<4>(key, idx, lane);
+            else if (d <= 8) bitonic_lanes<8>(key, idx, lane);
+            else if (d <= 16) bitonic_lanes<16>(key, idx, lane);
+            else if (d <= 32) bitonic_lanes<32>(key, idx, lane);
+            else bitonic_lanes<64>(key, idx, lane);
+            // rowQ of the vertex that lands on this lane, from the lane that loaded it
+            const int4 qv = make_int4(__shfl(qw.x, idx, 64), __shfl(qw.y, idx, 64), 0, __shfl(qw.w, idx, 64));
+            int64_t wu = 0;
+            if (in) {
+                const int32_t v = (int32_t)(uint32_t)key;
+                colO[rs + lane] = v;
+                pair_work(rs, d, lane, v, qv, true, vcap, packU, packD, cw, wu, gsum);
+            }
+            if (ballot64(wu != 0)) wu = wave_sum(wu);
+            if (lane == l) mine = wu;
+        }
+        if (x < n) Wu[x] = mine;
+    }
+    add_gather(gsum, acc);
+}
+
+// Anchor work of the light sources with d+ > 64, one wave per list: lists of
+// at most kSortCap entries are sorted into rank order by a bitonic network in
+// LDS and written back; longer ones keep their order.  Writes Wu of its lists
+// only (after k_work_lanes).
+__global__ void __launch_bounds__(256) k_work_lds(int64_t n, const int4* __restrict__ rowQ,
+                                                   int32_t* __restrict__ colO, int32_t vcap,
+                                                   int2* __restrict__ packU, int2* __restrict__ packD,
+                                                   unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
+                                                   int64_t* __restrict__ acc) {
+    __shared__ uint64_t keys[4][kSortCap];
+    const int lane = __lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint64_t* sk = keys[wv];
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    int64_t gsum = 0;
+    for (int64_t x0 = gw * 64; x0 < n; x0 += nw * 64) {
+        const int64_t x = x0 + lane;
+        const int4 q = x < n ? rowQ[x] : make_int4(0, 0, 0, 0);
+        uint64_t todo = ballot64(q.y > 64);
+        while (todo) {
+            const int l = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int32_t rs = __builtin_amdgcn_readlane(q.x, l);
+            const int32_t d = __builtin_amdgcn_readlane(q.y, l);
+            int64_t wu = 0;
+            if (d <= kSortCap) {
+                int G = 128;
+                while (G < d) G <<= 1;
+                constexpr int R = kSortCap / 64;
+                int32_t w[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = lane + 64 * r;
+                    w[r] = i < d ? colO[rs + i] : 0;
                 }
-            } else {
-                const int2 ry = rowD[y];
-                if (ry.y > 0) {  // y is a light source, ry.y = d+(y)
-                    const int32_t ck = rowD[key].y;
-                    if (vmajor(ry.y, ck >= 0 ? ck : ~ck, vcap)) {
-                        valid = true;
-                        val = ry.y;
-                        pk = make_int2(ry.x, ry.y);
+                int32_t dg[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) dg[r] = lane + 64 * r < d ? rowQ[w[r]].z : 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = lane + 64 * r;
+                    if (i < G) sk[i] = i < d ? rank_key(dg[r], w[r]) : ~0ull;
+                }
+                wave_lds_sync();
+                for (int K = 2; K <= G; K <<= 1) {
+                    for (int J = K >> 1; J > 0; J >>= 1) {
+                        for (int t = lane; t < (G >> 1); t += 64) {
+                            const int i = ((t & ~(J - 1)) << 1) | (t & (J - 1));  // bit J of i clear
+                            const uint64_t a = sk[i], b = sk[i | J];
+                            if ((i & K) == 0 ? a > b : a < b) {
+                                sk[i] = b;
+                                sk[i | J] = a;
+                            }
+                        }
+                        wave_lds_sync();
                     }
                 }
+                for (int k = lane; k < d; k += 64) {
+                    const int32_t v = (int32_t)(uint32_t)sk[k];
+                    const int4 qv = rowQ[v];
+                    colO[rs + k] = v;
+                    pair_work(rs, d, k, v, qv, true, vcap, packU, packD, cw, wu, gsum);
+                }
+                wave_lds_sync();  // keys read before the next list overwrites them
+            } else {
+                for (int k = lane; k < d; k += 64) {
+                    const int32_t v = colO[rs + k];
+                    pair_work(rs, d, k, v, rowQ[v], false, vcap, packU, packD, cw, wu, gsum);
+                }
             }
-            pack[e] = pk;
-        }
-        int64_t sum;
-        const bool tail = run_tail_sum(valid ? key : -1, valid, val, &sum);
-        if (tail) atomicAdd((unsigned long long*)&W[key], (unsigned long long)sum);
-    }
-    if (!down) {
-        gsum = wave_sum(gsum);
-        __shared__ int64_t red[4];
-        if (__lane_id() == 0) red[threadIdx.x >> 6] = gsum;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const int64_t t = red[0] + red[1] + red[2] + red[3];
-            if (t) atomicAdd((unsigned long long*)&acc[kGather], (unsigned long long)t);
+            wu = wave_sum(wu);
+            if (lane == 0) Wu[x0 + l] = wu;
         }
     }
+    add_gather(gsum, acc);
 }
 
 __device__ __forceinline__ int32_t items_of(int64_t w, int32_t len) {
     return w > 0 ? (len + kJL - 1) / kJL : 0;
 }
 
+// Length total and count of x's v-major descriptors.
+__device__ __forceinline__ int64_t cw_len(unsigned long long c) { return (int64_t)(c & 0xFFFFFFFFull); }
+__device__ __forceinline__ int32_t cw_cnt(unsigned long long c) { return (int32_t)(c >> 32); }
+
 // per vertex: item counts of the two bins (wave / block anchors), statistics
 // and the model bytes of each light kernel:
 //   per item: anchor row offsets (8 B) + staging N+(anchor) (4 B per entry);
-//   per iterated entry: the entry (4 B) + row offsets of its list (8 B)
-//   (+ 4 B code for down lists); per probe: the streamed entry (4 B).
+//   per iterated descriptor (d+ of them for u-major, the v-major count): 8 B;
+//   per probe: the streamed entry (4 B).
 __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __restrict__ code,
-                                                   const int32_t* __restrict__ dplus, const int32_t* __restrict__ dminus,
-                                                   const int64_t* __restrict__ Wu, const int64_t* __restrict__ Wv,
+                                                   const int32_t* __restrict__ dplus, const int64_t* __restrict__ Wu,
+                                                   const unsigned long long* __restrict__ cw,
                                                    int32_t small_dmax, int32_t* __restrict__ nsm,
                                                    int32_t* __restrict__ nlg, int32_t* __restrict__ nhg,
                                                    int64_t* __restrict__ part) {
@@ -256,11 +409,13 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
         const int32_t c = code[x];
         const int32_t dp = dplus[x];
         if (c > 0) { st[0] += 1; st[1] += c; st[2] += (int64_t)c * (c - 1) / 2; }
-        const int64_t wu = Wu[x], wv = Wv[x];
+        const unsigned long long c2 = cw[x];
+        const int64_t wu = Wu[x], wv = cw_len(c2);
+        const int32_t nv = cw_cnt(c2);
         const int32_t cu = items_of(wu, dp);
-        const int32_t cv = items_of(wv, dminus[x]);
-        const int64_t bytes = (int64_t)(cu + cv) * (8 + 4 * (int64_t)dp) + (wu > 0 ? 12 * (int64_t)dp : 0) +
-                              (wv > 0 ? 16 * (int64_t)dminus[x] : 0) + 4 * (wu + wv);
+        const int32_t cv = items_of(wv, nv);
+        const int64_t bytes = (int64_t)(cu + cv) * (8 + 4 * (int64_t)dp) + (wu > 0 ? 8 * (int64_t)dp : 0) +
+                              8 * (int64_t)(cv > 0 ? nv : 0) + 4 * (wu + wv);
         st[3] += wu + wv;
         const bool small = dp <= small_dmax;
         const bool huge = dp > kLdsDcap;
@@ -296,15 +451,16 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
 }
 
 // items of anchor x: (x, r) for the u-major ranges r of N+(x), then (~x, r)
-// for the v-major ranges r of N-(x)
+// for the ranges r of x's v-major descriptors
 __global__ void k_items(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ base,
-                        const int32_t* __restrict__ dplus, const int32_t* __restrict__ dminus,
-                        const int64_t* __restrict__ Wu, const int64_t* __restrict__ Wv, int2* __restrict__ items) {
+                        const int32_t* __restrict__ dplus, const int64_t* __restrict__ Wu,
+                        const unsigned long long* __restrict__ cw, int2* __restrict__ items) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         if (cnt[x] == 0) continue;
         int32_t b = base[x];
         const int32_t cu = items_of(Wu[x], dplus[x]);
-        const int32_t cv = items_of(Wv[x], dminus[x]);
+        const unsigned long long c2 = cw[x];
+        const int32_t cv = items_of(cw_len(c2), cw_cnt(c2));
         for (int32_t r = 0; r < cu; ++r) items[b++] = make_int2((int32_t)x, r);
         for (int32_t r = 0; r < cv; ++r) items[b++] = make_int2(~(int32_t)x, r);
     }
@@ -398,21 +554,6 @@ __device__ __forceinline__ int find_list(const int32_t* P, int d, int32_t g) {
     return lo;
 }
 
-// Orders one wave's shared-table writes before its later reads.  LDS
-// operations of a wave complete in order, so for tables in LDS only the
-// compiler must be kept from moving accesses across (fences) and outstanding
-// LDS results are drained (lgkmcnt); global loads stay in flight.  Tables in
-// global scratch (GLOBAL) need every outstanding access drained.
-template <bool GLOBAL>
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    if (GLOBAL) __builtin_amdgcn_s_waitcnt(0);
-    else __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt unrestricted
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ void wave_lds_sync() { wave_sync<false>(); }
 
 // Membership tests of the keys x[k] of the lanes in the wave mask vm[k]
 // against the bucketed table; returns the number of hits in the whole wave
@@ -662,8 +803,10 @@ template <int DS>
 __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ items,
                                                       const int32_t* __restrict__ n_items_dev,
                                                       const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
-                                                      const int32_t* __restrict__ rpD, const int2* __restrict__ packU,
-                                                      const int2* __restrict__ packD, int64_t* __restrict__ acc) {
+                                                      const int32_t* __restrict__ rpD,
+                                                      const unsigned long long* __restrict__ cw,
+                                                      const int2* __restrict__ packU, const int2* __restrict__ packD,
+                                                      int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 4 * DS;                                     // buckets of 4 slots, load <= 1/4
     constexpr int ROW = (HS_MAX + 2 * kJL + 1 + 64 * kU + 3) / 4 * 4;  // keeps every row 16-byte aligned
     constexpr int KR = (DS + 63) / 64;                                 // keys per lane
@@ -689,7 +832,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         d = rpO[x + 1] - rs;
         int32_t llen;
         if (kind_u) { L = packU + rs; llen = d; }
-        else { const int32_t ds = rpD[x]; L = packD + ds; llen = rpD[x + 1] - ds; }
+        else { L = packD + rpD[x]; llen = cw_cnt(cw[x]); }
         const int32_t j0 = item.y * kJL;
         L += j0;
         cnt = min(kJL, llen - j0);
@@ -747,8 +890,10 @@ template <bool GLOBAL>
 __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ items,
                                                       const int32_t* __restrict__ n_items_dev,
                                                       const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
-                                                      const int32_t* __restrict__ rpD, const int2* __restrict__ packU,
-                                                      const int2* __restrict__ packD, int32_t dcap,
+                                                      const int32_t* __restrict__ rpD,
+                                                      const unsigned long long* __restrict__ cw,
+                                                      const int2* __restrict__ packU, const int2* __restrict__ packD,
+                                                      int32_t dcap,
                                                       int32_t* __restrict__ gscratch, int64_t* __restrict__ acc) {
     extern __shared__ __attribute__((aligned(16))) int32_t dyn[];
     __shared__ int32_t red[5];
@@ -775,7 +920,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         const int2* L;
         int32_t llen;
         if (kind_u) { L = packU + rs; llen = d; }
-        else { const int32_t ds = rpD[x]; L = packD + ds; llen = rpD[x + 1] - ds; }
+        else { L = packD + rpD[x]; llen = cw_cnt(cw[x]); }
         const int32_t j0 = item.y * kJL;
         const int32_t cnt = min(kJL, llen - j0);
         const int lg = bucket_bits(d);
@@ -1045,45 +1190,44 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         E2_dev = kpre.get() + NW;  // 2 m'
     }
 
-    // 2. orientation by (deg, id): compacted up lists N+(x) and down lists N-(x)
-    DevBuf<uint64_t> ubits(NW, s), dbits(NW, s);
-    DevBuf<int32_t> upre(NW + 1, s), dpre(NW + 1, s);
+    // 2. orientation by (deg, id): compacted up lists N+(x), in CSR order
+    DevBuf<uint64_t> ubits(NW, s);
+    DevBuf<int32_t> upre(NW + 1, s);
     TC_LAUNCH("orient_bits", k_orient_bits, dim3(grid_for(NW, 16)), dim3(256), 0, s, v_src, v_col, E2, E2_dev, degp,
-              ubits.get(), upre.get(), dbits.get(), dpre.get());
+              ubits.get(), upre.get());
     scan_exclusive_i32(upre.get(), upre.get(), NW, s);
-    scan_exclusive_i32(dpre.get(), dpre.get(), NW, s);
     const int32_t* mp_dev = upre.get() + NW;  // number of up entries = m'
-    DevBuf<int32_t> rpO(n + 1, s), dplus(n, s), rpD(n + 1, s), dminus(n, s);
+    DevBuf<int32_t> rpO(n + 1, s), dplus(n, s);
     positions_at_rows(v_row, n, E2, ubits.get(), upre.get(), rpO.get(), dplus.get(), s);
-    positions_at_rows(v_row, n, E2, dbits.get(), dpre.get(), rpD.get(), dminus.get(), s);
-    // m' <= m: size the lists by m
-    DevBuf<int32_t> colO(g->m, s), srcO(g->m, s), colD(g->m, s), srcD(g->m, s);
-    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), srcO.get(), s, E2_dev);
-    compact_kept(v_col, v_src, E2, dbits.get(), dpre.get(), colD.get(), srcD.get(), s, E2_dev);
+    DevBuf<int32_t> colO(g->m, s);  // m' <= m
+    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), nullptr, s, E2_dev);
 
-    // 3. classification, anchor work, item lists
+    // 3. classification; anchor work (each light source's N+(u) in rank
+    //    order, one descriptor per pair); item lists
     const int32_t vcap = cfg.vmajor_cap;
-    DevBuf<int32_t> heavy(n + 1, s), code(n, s);
-    DevBuf<int2> rowD(n, s);
+    DevBuf<int32_t> heavy(n + 1, s), code(n, s), dminus(n, s), rpD(n + 1, s);
     TC_LAUNCH("vertex_prep", k_vertex_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, n, degp,
-              (const int32_t*)dplus.get(), (const int32_t*)rpO.get(), mp_dev, cfg.heavy_num, cfg.heavy_den,
-              heavy.get(), code.get(), rowD.get());
-    DevBuf<int64_t> Wu(n, s), Wv(n, s);
-    fill_i64(Wu.get(), 0, n, s);
-    fill_i64(Wv.get(), 0, n, s);
-    const unsigned wgrid = std::min<unsigned>(grid_for(g->m, 256), 8192u);
+              (const int32_t*)dplus.get(), mp_dev, cfg.heavy_num, cfg.heavy_den, heavy.get(), code.get(),
+              dminus.get());
+    scan_exclusive_i32(dminus.get(), rpD.get(), n, s);  // slots of each vertex's v-major descriptors
+    DevBuf<int4> rowQ(n, s);
+    TC_LAUNCH("row_q", k_row_q, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)rpO.get(),
+              (const int32_t*)code.get(), (const int32_t*)dplus.get(), degp, (const int32_t*)rpD.get(), rowQ.get());
+    DevBuf<int64_t> Wu(n, s), cw(n, s);
+    fill_i64(cw.get(), 0, n, s);
+    unsigned long long* cwp = reinterpret_cast<unsigned long long*>(cw.get());
     DevBuf<int2> packU(g->m, s), packD(vcap > 0 ? g->m : 1, s);
-    TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcO.get(), (const int32_t*)colO.get(),
-              mp_dev, (const int2*)rowD.get(), vcap, 0, Wu.get(), packU.get(), acc);
-    if (vcap > 0)
-        TC_LAUNCH("work", k_work, dim3(wgrid), dim3(256), 0, s, (const int32_t*)srcD.get(), (const int32_t*)colD.get(),
-                  mp_dev, (const int2*)rowD.get(), vcap, 1, Wv.get(), packD.get(), acc);
+    TC_LAUNCH("work", k_work_lanes, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int4*)rowQ.get(),
+              colO.get(), vcap, packU.get(), packD.get(), cwp, Wu.get(), acc);
+    if (g->max_deg > 64)  // bounds every d+
+        TC_LAUNCH("work_lds", k_work_lds, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int4*)rowQ.get(),
+                  colO.get(), vcap, packU.get(), packD.get(), cwp, Wu.get(), acc);
     DevBuf<int32_t> nsm(n + 1, s), nlg(n + 1, s), nhg(n + 1, s);
     const unsigned cgrid = std::min<unsigned>(grid_for(n, 256), kClassifyBlocks);
     DevBuf<int64_t> cpart((size_t)cgrid * 9, s);
     TC_LAUNCH("classify", k_classify, dim3(cgrid), dim3(256), 0, s, n, (const int32_t*)code.get(),
-              (const int32_t*)dplus.get(), (const int32_t*)dminus.get(), (const int64_t*)Wu.get(),
-              (const int64_t*)Wv.get(), cfg.small_dmax, nsm.get(), nlg.get(), nhg.get(), cpart.get());
+              (const int32_t*)dplus.get(), (const int64_t*)Wu.get(), (const unsigned long long*)cwp, cfg.small_dmax,
+              nsm.get(), nlg.get(), nhg.get(), cpart.get());
     DevBuf<int32_t> sbase(n + 1, s), lbase(n + 1, s), hbase(n + 1, s), hpos(n + 1, s);
     scan_exclusive_i32(nsm.get(), sbase.get(), n, s);
     scan_exclusive_i32(nlg.get(), lbase.get(), n, s);
@@ -1096,8 +1240,8 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     {
         DevBuf<int2> items(items_max, s);
         TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)nsm.get(),
-                  (const int32_t*)sbase.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
-                  (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
+                  (const int32_t*)sbase.get(), (const int32_t*)dplus.get(), (const int64_t*)Wu.get(),
+                  (const unsigned long long*)cwp, items.get());
         // a persistent grid larger than what stays resident would run its last
         // blocks in a second round: cap the blocks per CU at the resident count
         static const int resident = [] {
@@ -1110,14 +1254,14 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         const int64_t blocks = (int64_t)num_cus() * std::min<int32_t>(cfg.light_blocks_per_cu, resident);
         TC_LAUNCH("light_small", k_light_small<128>, dim3((unsigned)blocks), dim3(256), 0, s,
                   (const int2*)items.get(), (const int32_t*)sbase.get() + n, (const int32_t*)rpO.get(),
-                  (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const int2*)packU.get(),
-                  (const int2*)packD.get(), acc);
+                  (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
+                  (const int2*)packU.get(), (const int2*)packD.get(), acc);
     }
     auto launch_large = [&](const DevBuf<int32_t>& cnt, const DevBuf<int32_t>& base, int32_t dcap, bool global) {
         DevBuf<int2> items(items_max, s);
         TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)cnt.get(),
-                  (const int32_t*)base.get(), (const int32_t*)dplus.get(), (const int32_t*)dminus.get(),
-                  (const int64_t*)Wu.get(), (const int64_t*)Wv.get(), items.get());
+                  (const int32_t*)base.get(), (const int32_t*)dplus.get(), (const int64_t*)Wu.get(),
+                  (const unsigned long long*)cwp, items.get());
         // tab: 4 * next_pow2(d) <= 4 * dcap slots, P: kJL+1, D: kJL, flags: 4*64*kU (16-byte multiple)
         const size_t per_block = (size_t)large_block_words(dcap);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
@@ -1138,15 +1282,15 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
             const int64_t blocks = (int64_t)num_cus() * per_cu;
             TC_LAUNCH("light_large", k_light_large<false>, dim3((unsigned)blocks), dim3(256), lds_bytes, s,
                       (const int2*)items.get(), (const int32_t*)base.get() + n, (const int32_t*)rpO.get(),
-                      (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const int2*)packU.get(),
-                      (const int2*)packD.get(), dcap, (int32_t*)nullptr, acc);
+                      (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
+                      (const int2*)packU.get(), (const int2*)packD.get(), dcap, (int32_t*)nullptr, acc);
         } else {
             const int64_t blocks = (int64_t)num_cus();
             DevBuf<int32_t> gscr((size_t)blocks * per_block, s);
             TC_LAUNCH("light_huge", k_light_large<true>, dim3((unsigned)blocks), dim3(256), 0, s,
                       (const int2*)items.get(), (const int32_t*)base.get() + n, (const int32_t*)rpO.get(),
-                      (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const int2*)packU.get(),
-                      (const int2*)packD.get(), dcap, gscr.get(), acc);
+                      (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
+                      (const int2*)packU.get(), (const int2*)packD.get(), dcap, gscr.get(), acc);
         }
     };
     const LightPlan plan = light_plan(g->m, maxd, cfg);
@@ -1208,11 +1352,11 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     const int64_t NW = (E2 + 63) / 64;
     if (sampled)
         b += rb(8 * NW) + rb(4 * (NW + 1)) + rb(4 * (n + 1)) + rb(4 * n) + 2 * rb(4 * E2) + scan_scratch_bytes(NW);
-    b += 2 * rb(8 * NW) + 2 * rb(4 * (NW + 1)) + 2 * scan_scratch_bytes(NW);  // orientation bits, prefixes
-    b += 2 * rb(4 * (n + 1)) + 2 * rb(4 * n);                                 // rpO, d+, rpD, d-
-    b += 4 * rb(4 * m);                                                        // up and down lists
-    b += rb(4 * (n + 1)) + rb(4 * n) + rb(8 * n) + 2 * rb(8 * n);              // heavy, code, rowD, Wu, Wv
-    b += rb(8 * m) + rb(8 * (cfg.vmajor_cap > 0 ? m : 1));                     // packed descriptors
+    b += rb(8 * NW) + rb(4 * (NW + 1)) + scan_scratch_bytes(NW);  // orientation bits, prefixes
+    b += rb(4 * (n + 1)) + rb(4 * n) + rb(4 * m);                  // rpO, d+, up lists
+    b += 2 * rb(4 * (n + 1)) + 2 * rb(4 * n) + scan_scratch_bytes(n);  // heavy, code, d-, descriptor slots
+    b += rb(16 * n) + 2 * rb(8 * n);                               // rowQ, Wu, cw
+    b += rb(8 * m) + rb(8 * (cfg.vmajor_cap > 0 ? m : 1));         // packed descriptors
     b += 7 * rb(4 * (n + 1)) + 4 * scan_scratch_bytes(n);                      // item counts and bases
     b += rb(8 * 9 * (int64_t)std::min<int64_t>((n + 255) / 256, kClassifyBlocks));  // classification partials
     const int64_t items_max = 2 * n + E2 / kJL + 2;

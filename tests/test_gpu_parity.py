@@ -7,6 +7,7 @@ import sys
 import numpy as np
 import pytest
 
+import light_schedule
 import oracle
 import synth
 from synth import special
@@ -207,9 +208,32 @@ def test_counts_invariant_under_launch_tunings(gpu, name):
                 got = gpu.tc_estimate(g, p, [3], tuned=True)[0][0]
             for k in ("triangles", "light", "heavy", "n_heavy", "m"):
                 assert got[k] == wp[k], (name, p, t, k, got[k], wp[k])
-            assert got["probes"] <= got["gather"]
-            if t["vmajor_cap"] == 0:
-                assert got["probes"] == got["gather"]
+            sched = light_schedule.light_work(og if p == 1.0 else oracle.sample(og, p, 3), 1, 1, t["vmajor_cap"])
+            assert (got["probes"], got["gather"]) == (sched["probes"], sched["gather"]), (name, p, t, sched)
+
+
+@pytest.mark.parametrize("vcap", [0, 1024, 1 << 30])
+def test_long_out_lists_sorted_and_unsorted(gpu, vcap):
+    # K_1100, all light: out-lists of every length up to 1099, so lists of the
+    # register sort (<= 64), of the LDS sort (65..1024) and unsorted ones
+    # (> 1024) all occur; exact count and the schedule's work statistics
+    n = 1100
+    G = special.complete(n)
+    g = _build(gpu, G)
+    og = oracle.normalise(*G)
+    gpu.tc_tune_set(g, 1.0, heavy=(1000, 1), vmajor_cap=vcap, small_dmax=128, blocks_per_cu=2)
+    _log("K_1100 vcap=%d" % vcap)
+    got = gpu.tc_count_exact(g, tuned=True)
+    assert got["triangles"] == got["light"] == math.comb(n, 3) and got["n_heavy"] == 0
+    sched = light_schedule.light_work(og, 1000, 1, vcap)
+    assert (got["probes"], got["gather"]) == (sched["probes"], sched["gather"]), sched
+    for p, seed in ((0.5, 7), (0.9, 8)):
+        gpu.tc_tune_set(g, p, heavy=(1000, 1), vmajor_cap=vcap, small_dmax=128, blocks_per_cu=2)
+        gs = oracle.sample(og, p, seed)
+        r = gpu.tc_estimate(g, p, [seed], tuned=True)[0][0]
+        assert r["triangles"] == oracle.count(gs)
+        s2 = light_schedule.light_work(gs, 1000, 1, vcap)
+        assert (r["probes"], r["gather"]) == (s2["probes"], s2["gather"]), (p, s2)
 
 
 def test_autotune_keeps_the_count(gpu):
