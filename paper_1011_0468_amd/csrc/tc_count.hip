@@ -165,19 +165,23 @@ __global__ void k_vertex_prep(int64_t n, const int32_t* __restrict__ degp, const
     }
 }
 
-// rowQ[x] = (start of N+(x), code ? d+ : ~d+, deg, start of x's v-major
-// descriptors): everything the anchor work needs of a vertex in one 16-byte load
+// rowQ[x] = (start of N+(x), code ? d+ : ~d+, deg, 0): everything the anchor
+// work needs of a vertex in one 16-byte load; cw[x] = rpD[x] << 32, the first
+// slot of x's v-major descriptors (see claim_vmajor)
 __global__ void k_row_q(int64_t n, const int32_t* __restrict__ rpO, const int32_t* __restrict__ code,
                         const int32_t* __restrict__ dplus, const int32_t* __restrict__ degp,
-                        const int32_t* __restrict__ rpD, int4* __restrict__ rowQ) {
+                        const int32_t* __restrict__ rpD, int4* __restrict__ rowQ,
+                        unsigned long long* __restrict__ cw) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = code[x];
-        rowQ[x] = make_int4(rpO[x], c ? c : ~dplus[x], degp[x], rpD[x]);
+        rowQ[x] = make_int4(rpO[x], c ? c : ~dplus[x], degp[x], 0);
+        cw[x] = (unsigned long long)(uint32_t)rpD[x] << 32;
     }
 }
 
 // Longest out-list that the anchor work sorts into rank order (one wave, in
-// LDS).  A longer list keeps CSR order and each of its pairs streams all of it.
+// registers).  A longer list keeps CSR order and each of its pairs streams all
+// of it.
 constexpr int kSortCap = 1024;
 
 // The rank (deg, id) as one unsigned integer: rank_below(du, u, dv, v) iff
@@ -186,31 +190,28 @@ __device__ __forceinline__ uint64_t rank_key(int32_t deg, int32_t w) {
     return ((uint64_t)(uint32_t)deg << 32) | (uint32_t)w;
 }
 
-// One pair (u, v) of the anchor work: v is entry k of N+(u) (rs = start of
-// N+(u), d = d+(u)), qv = rowQ[v].  If N+(u) is in rank order, only its
-// entries after k can close (u, v) (a common out-neighbour w of u and v ranks
-// above v); a pair with none is skipped.  The pair's descriptor goes to
-// packU[rs + k] (u-major: (start of N+(v), d+(v)); else (0, 0)) or, v-major,
-// to the next free slot of v's descriptors (start and length of the streamed
-// part of N+(u)).  cw[v] accumulates (count << 32) + total length of v's
-// descriptors with one atomic: lengths sum to at most m' < 2^31.
-__device__ __forceinline__ void pair_work(int32_t rs, int32_t d, int32_t k, int32_t v, int4 qv, bool sorted,
-                                          int32_t vcap, int2* __restrict__ packU, int2* __restrict__ packD,
-                                          unsigned long long* __restrict__ cw, int64_t& wu, int64_t& gsum) {
+// The descriptor of pair (u, v) of the anchor work, for packU[rs + k]: v is
+// entry k of N+(u) (rs = start of N+(u), d = d+(u)), qv = rowQ[v].  If N+(u)
+// is in rank order, only its entries after k can close (u, v) (a common
+// out-neighbour w of u and v ranks above v), and a pair with none gets (0, 0).
+// u-major: (start of N+(v), d+(v)).  v-major: (start of the streamed part of
+// N+(u), minus its length), placed by the caller through claim_vmajor.
+__device__ __forceinline__ int2 pair_desc(int32_t rs, int32_t d, int32_t k, int4 qv, bool sorted, int32_t vcap,
+                                          int64_t& wu, int64_t& gsum) {
     const int32_t dv = qv.y >= 0 ? qv.y : ~qv.y;
     gsum += dv;
     const int32_t len = sorted ? d - 1 - k : d;
-    int2 pk = make_int2(0, 0);
-    if (len > 0) {
-        if (vmajor(len, dv, vcap)) {
-            const unsigned long long old = atomicAdd(&cw[v], (1ull << 32) | (uint32_t)len);
-            packD[qv.w + (int32_t)(old >> 32)] = make_int2(sorted ? rs + k + 1 : rs, len);
-        } else {
-            pk = make_int2(qv.x, dv);
-            wu += dv;
-        }
-    }
-    packU[rs + k] = pk;
+    if (len <= 0) return make_int2(0, 0);
+    if (vmajor(len, dv, vcap)) return make_int2(sorted ? rs + k + 1 : rs, -len);
+    wu += dv;
+    return make_int2(qv.x, dv);
+}
+
+// Claim the next slot of v's v-major descriptors: one atomic on cw[v], which
+// starts at rpD[v] << 32 and gains (1 << 32) + length per descriptor (the
+// lengths of one vertex sum to at most m' < 2^31); returns the slot.
+__device__ __forceinline__ int64_t claim_vmajor(unsigned long long* cw, int32_t v, int32_t len) {
+    return (int64_t)(atomicAdd(&cw[v], (1ull << 32) | (uint32_t)len) >> 32);
 }
 
 // lane ^ J exchange (J a power of two below 64)
@@ -220,28 +221,80 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
     else return (uint32_t)__shfl_xor((int)v, J, 64);
 }
 
-// Merge steps J, J/2, .., 1 of the bitonic network's stage K over lanes
-// (key, idx pairs; runs of K lanes alternate ascending and descending).
-template <int K, int J>
+template <int J>
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v) {
+    return ((uint64_t)lane_xor<J>((uint32_t)(v >> 32)) << 32) | lane_xor<J>((uint32_t)v);
+}
+
+// c ? a : b as two 32-bit selects (keeps the sorting networks free of branches)
+__device__ __forceinline__ uint64_t sel64(bool c, uint64_t a, uint64_t b) {
+    const uint32_t lo = c ? (uint32_t)a : (uint32_t)b;
+    const uint32_t hi = c ? (uint32_t)(a >> 32) : (uint32_t)(b >> 32);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Merge steps J, J/2, .., 1 of stage K of a bitonic network over each aligned
+// group of G lanes (key, idx pairs): runs of K lanes alternate ascending and
+// descending, and the last stage (K = G) sorts every group ascending.
+template <int G, int K, int J>
 __device__ __forceinline__ void bitonic_steps(uint64_t& key, int32_t& idx, int lane) {
     if constexpr (J > 0) {
-        const uint64_t ok = ((uint64_t)lane_xor<J>((uint32_t)(key >> 32)) << 32) | lane_xor<J>((uint32_t)key);
+        const uint64_t ok = lane_xor64<J>(key);
         const int32_t oi = (int32_t)lane_xor<J>((uint32_t)idx);
-        const bool keep_min = ((lane & K) == 0) == ((lane & J) == 0);
-        if (keep_min ? ok < key : ok > key) {
-            key = ok;
-            idx = oi;
-        }
-        bitonic_steps<K, J / 2>(key, idx, lane);
+        const bool asc = K == G || (lane & K) == 0;
+        const bool keep_min = asc == ((lane & J) == 0);
+        const bool take = (ok < key) == keep_min;  // equal keys are interchangeable padding
+        key = sel64(take, ok, key);
+        idx = take ? oi : idx;
+        bitonic_steps<G, K, J / 2>(key, idx, lane);
     }
 }
 
-// Ascending sort of the keys of lanes [0, G) (G a power of two <= 64), each
-// carrying idx along.  Lanes at or past G take part in runs of their own.
+// Ascending sort of the keys within each aligned group of G lanes (G a power
+// of two <= 64), each key carrying idx along.
 template <int G, int K = 2>
 __device__ __forceinline__ void bitonic_lanes(uint64_t& key, int32_t& idx, int lane) {
-    bitonic_steps<K, K / 2>(key, idx, lane);
+    bitonic_steps<G, K, K / 2>(key, idx, lane);
     if constexpr (K < G) bitonic_lanes<G, 2 * K>(key, idx, lane);
+}
+
+// Merge steps J, .., 1 of stage K of a bitonic network over the 64 R keys of
+// a wave held as position i = lane + 64 r (r < R): partners 64 apart or more
+// sit in the same lane (a register swap), closer ones in the same register
+// (a lane exchange).
+template <int R, int K, int J>
+__device__ __forceinline__ void wide_steps(uint64_t (&key)[R], int lane) {
+    if constexpr (J > 0) {
+        if constexpr (J >= 64) {
+            constexpr int D = J / 64;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if ((r & D) == 0) {
+                    const bool asc = ((64 * r) & K) == 0;
+                    const uint64_t a = key[r], b = key[r | D];
+                    const bool sw = (b < a) == asc;
+                    key[r] = sel64(sw, b, a);
+                    key[r | D] = sel64(sw, a, b);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t ok = lane_xor64<J>(key[r]);
+                const bool asc = ((lane + 64 * r) & K) == 0;
+                const bool keep_min = asc == ((lane & J) == 0);
+                key[r] = sel64((ok < key[r]) == keep_min, ok, key[r]);
+            }
+        }
+        wide_steps<R, K, J / 2>(key, lane);
+    }
+}
+
+// Ascending sort of 64 R keys, position i = lane + 64 r.
+template <int R, int K = 2>
+__device__ __forceinline__ void bitonic_wide(uint64_t (&key)[R], int lane) {
+    wide_steps<R, K, K / 2>(key, lane);
+    if constexpr (K < 64 * R) bitonic_wide<R, 2 * K>(key, lane);
 }
 
 // Block reduction of the gather statistic into acc (256 threads).
@@ -256,16 +309,182 @@ __device__ __forceinline__ void add_gather(int64_t gsum, int64_t* acc) {
     }
 }
 
-// Anchor work of the light sources with d+ <= 64, one wave per list: N+(u) is
-// sorted into rank order in registers and written back, and each of its pairs
-// gets its descriptor (pair_work).  Each wave takes 64 consecutive vertices
-// per step and writes Wu (the length u-major pairs stream) of all of them, 0
-// for the lists left to k_work_lds.
+// The lists of one 64-vertex window (q = rowQ of this lane's vertex) in mask
+// whose lengths fit G lanes: 64 / G lists at a time, one per aligned group of
+// G lanes, each sorted into rank order and written back, with the
+// descriptors of its pairs and its Wu.
+template <int G>
+__device__ __forceinline__ void work_groups(uint64_t mask, const int4& q, int64_t x0, int lane,
+                                            const int4* __restrict__ rowQ, int32_t* __restrict__ colO, int32_t vcap,
+                                            int2* __restrict__ packU, int2* __restrict__ packD,
+                                            unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
+                                            int64_t& gsum) {
+    constexpr int P = 64 / G;
+    const int grp = lane / G;
+    const int pos = lane & (G - 1);
+    while (mask) {
+        int mine = -1;  // window lane of this group's list
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            if (mask) {
+                const int l = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                if (grp == j) mine = l;
+            }
+        }
+        // both shuffles run in every lane: a lane reads a list's length from
+        // the window lane that holds it, which need not own a list itself
+        const int sl = mine < 0 ? 0 : mine;
+        const int32_t rs = __shfl(q.x, sl, 64);
+        const int32_t dl = __shfl(q.y, sl, 64);
+        const int32_t d = mine < 0 ? 0 : dl;
+        const bool in = pos < d;
+        const int32_t w = in ? colO[rs + pos] : 0;
+        const int4 qw = in ? rowQ[w] : make_int4(0, 0, 0, 0);
+        uint64_t key = in ? rank_key(qw.z, w) : ~0ull;
+        int32_t idx = lane;
+        bitonic_lanes<G>(key, idx, lane);
+        // rowQ of the vertex that lands on this lane, from the lane that loaded it
+        const int4 qv = make_int4(__shfl(qw.x, idx, 64), __shfl(qw.y, idx, 64), 0, __shfl(qw.w, idx, 64));
+        int64_t wu = 0;
+        if (in) {
+            const int32_t v = (int32_t)(uint32_t)key;
+            colO[rs + pos] = v;
+            int2 pk = pair_desc(rs, d, pos, qv, true, vcap, wu, gsum);
+            if (pk.y < 0) {
+                packD[claim_vmajor(cw, v, -pk.y)] = make_int2(pk.x, -pk.y);
+                pk = make_int2(0, 0);
+            }
+            packU[rs + pos] = pk;
+        }
+#pragma unroll
+        for (int J = G / 2; J >= 1; J >>= 1) wu += __shfl_xor(wu, J, 64);
+        if (pos == 0 && mine >= 0) Wu[x0 + mine] = wu;
+    }
+}
+
+// Descriptors of up to B strips of 64 pairs of one list (v in the low half
+// of vk[b], at position k0 + 64 b + lane): all rowQ gathers first, then all
+// atomics, then the stores, so that a list waits for one round of each.
+template <int B>
+__device__ __forceinline__ void strip_work(const uint64_t (&vk)[B], int32_t k0, int32_t rs, int32_t d, bool sorted,
+                                           int lane, const int4* __restrict__ rowQ, int32_t* __restrict__ colO,
+                                           int32_t vcap, int2* __restrict__ packU, int2* __restrict__ packD,
+                                           unsigned long long* __restrict__ cw, int64_t& wu, int64_t& gsum) {
+    int4 qv[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int32_t k = k0 + 64 * b + lane;
+        qv[b] = k < d ? rowQ[(int32_t)(uint32_t)vk[b]] : make_int4(0, 0, 0, 0);
+    }
+    int2 pk[B];
+    int64_t slot[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int32_t k = k0 + 64 * b + lane;
+        pk[b] = k < d ? pair_desc(rs, d, k, qv[b], sorted, vcap, wu, gsum) : make_int2(0, 0);
+        slot[b] = pk[b].y < 0 ? claim_vmajor(cw, (int32_t)(uint32_t)vk[b], -pk[b].y) : 0;
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int32_t k = k0 + 64 * b + lane;
+        if (k < d) {
+            if (pk[b].y < 0) {
+                packD[slot[b]] = make_int2(pk[b].x, -pk[b].y);
+                pk[b] = make_int2(0, 0);
+            }
+            packU[rs + k] = pk[b];
+            if (sorted) colO[rs + k] = (int32_t)(uint32_t)vk[b];
+        }
+    }
+}
+
+// One list of 64 (R - 1) < d <= 64 R entries: loaded into registers
+// (position lane + 64 r), sorted into rank order, written back with the
+// descriptors of its pairs.  The rank keys come from rowQ, so that the
+// descriptors' rowQ gathers after the sort find their lines in the cache.
+template <int R>
+__device__ __forceinline__ void work_wide_list(int32_t rs, int32_t d, int lane, const int4* __restrict__ rowQ,
+                                               int32_t* __restrict__ colO, int32_t vcap, int2* __restrict__ packU,
+                                               int2* __restrict__ packD, unsigned long long* __restrict__ cw,
+                                               int64_t& wu, int64_t& gsum) {
+    int32_t w[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + 64 * r;
+        w[r] = i < d ? colO[rs + i] : 0;
+    }
+    uint64_t key[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + 64 * r;
+        key[r] = i < d ? rank_key(rowQ[w[r]].z, w[r]) : ~0ull;
+    }
+    bitonic_wide<R>(key, lane);
+    constexpr int B = R < 4 ? R : 4;
+#pragma unroll
+    for (int r0 = 0; r0 < R; r0 += B) {
+        uint64_t vk[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) vk[b] = key[r0 + b];
+        strip_work<B>(vk, 64 * r0, rs, d, true, lane, rowQ, colO, vcap, packU, packD, cw, wu, gsum);
+    }
+}
+
+// The lists of one window in mask, one wave per list, with 32 R < d <= 64 R
+// (R = 16 also takes the lists longer than kSortCap, which keep their order
+// and whose pairs stream all of N+(u)); writes their Wu.
+template <int R>
+__device__ __forceinline__ void work_wide_lists(uint64_t mask, const int4& q, int64_t x0, int lane,
+                                                const int4* __restrict__ rowQ, int32_t* __restrict__ colO,
+                                                int32_t vcap, int2* __restrict__ packU, int2* __restrict__ packD,
+                                                unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
+                                                int64_t& gsum) {
+    while (mask) {
+        const int l = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const int32_t rs = __builtin_amdgcn_readlane(q.x, l);
+        const int32_t d = __builtin_amdgcn_readlane(q.y, l);
+        int64_t wu = 0;
+        if (d <= 64 * R) {
+            work_wide_list<R>(rs, d, lane, rowQ, colO, vcap, packU, packD, cw, wu, gsum);
+        } else {
+            for (int32_t k0 = 0; k0 < d; k0 += 256) {
+                uint64_t vk[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int32_t k = k0 + 64 * b + lane;
+                    vk[b] = k < d ? (uint32_t)colO[rs + k] : 0;
+                }
+                strip_work<4>(vk, k0, rs, d, false, lane, rowQ, colO, vcap, packU, packD, cw, wu, gsum);
+            }
+        }
+        wu = wave_sum(wu);
+        if (lane == 0) Wu[x0 + l] = wu;
+    }
+}
+
+// Appends the vertices of mask (window x0) to list L (count at L[-1]):
+// one atomic per wave.
+__device__ __forceinline__ void append_rows(uint64_t mask, int64_t x0, int lane, int32_t* __restrict__ L) {
+    if (!mask) return;
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(&L[-1], (int32_t)__popcll(mask));
+    base = __shfl(base, 0, 64);
+    if ((mask >> lane) & 1ull) L[base + (int32_t)__popcll(mask & lanes_below())] = (int32_t)(x0 + lane);
+}
+
+// Anchor work of the light sources with d+ <= 128: each wave takes 64
+// consecutive vertices per step, sorts their lists of up to 64 entries in lane
+// groups of 4 to 64 and those of 65 to 128 entries in two registers per lane,
+// and writes Wu (the length u-major pairs stream) of all of them, 0 for the
+// longer lists, which it appends to the lists of k_work_wide's classes
+// (wide[c * (n + 1)] holds the count of class c, its vertices follow).
 __global__ void __launch_bounds__(256) k_work_lanes(int64_t n, const int4* __restrict__ rowQ,
                                                      int32_t* __restrict__ colO, int32_t vcap,
                                                      int2* __restrict__ packU, int2* __restrict__ packD,
                                                      unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
-                                                     int64_t* __restrict__ acc) {
+                                                     int32_t* __restrict__ wide, int64_t* __restrict__ acc) {
     const int lane = __lane_id();
     const int64_t gw = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * 4;
@@ -273,113 +492,40 @@ __global__ void __launch_bounds__(256) k_work_lanes(int64_t n, const int4* __res
     for (int64_t x0 = gw * 64; x0 < n; x0 += nw * 64) {
         const int64_t x = x0 + lane;
         const int4 q = x < n ? rowQ[x] : make_int4(0, 0, 0, 0);
-        int64_t mine = 0;
-        uint64_t todo = ballot64(q.y >= 2 && q.y <= 64);
-        while (todo) {
-            const int l = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const int32_t rs = __builtin_amdgcn_readlane(q.x, l);
-            const int32_t d = __builtin_amdgcn_readlane(q.y, l);
-            const bool in = lane < d;
-            const int32_t w = in ? colO[rs + lane] : 0;
-            const int4 qw = in ? rowQ[w] : make_int4(0, 0, 0, 0);
-            uint64_t key = in ? rank_key(qw.z, w) : ~0ull;
-            int32_t idx = lane;
-            if (d <= 4) bitonic_lanes<4>(key, idx, lane);
-            else if (d <= 8) bitonic_lanes<8>(key, idx, lane);
-            else if (d <= 16) bitonic_lanes<16>(key, idx, lane);
-            else if (d <= 32) bitonic_lanes<32>(key, idx, lane);
-            else bitonic_lanes<64>(key, idx, lane);
-            // rowQ of the vertex that lands on this lane, from the lane that loaded it
-            const int4 qv = make_int4(__shfl(qw.x, idx, 64), __shfl(qw.y, idx, 64), 0, __shfl(qw.w, idx, 64));
-            int64_t wu = 0;
-            if (in) {
-                const int32_t v = (int32_t)(uint32_t)key;
-                colO[rs + lane] = v;
-                pair_work(rs, d, lane, v, qv, true, vcap, packU, packD, cw, wu, gsum);
-            }
-            if (ballot64(wu != 0)) wu = wave_sum(wu);
-            if (lane == l) mine = wu;
-        }
-        if (x < n) Wu[x] = mine;
+        const int32_t d = q.y;
+        if (x < n && !(d >= 2 && d <= 128)) Wu[x] = 0;
+        work_groups<4>(ballot64(d >= 2 && d <= 4), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
+        work_groups<8>(ballot64(d > 4 && d <= 8), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
+        work_groups<16>(ballot64(d > 8 && d <= 16), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
+        work_groups<32>(ballot64(d > 16 && d <= 32), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
+        work_groups<64>(ballot64(d > 32 && d <= 64), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
+        work_wide_lists<2>(ballot64(d > 64 && d <= 128), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
+        append_rows(ballot64(d > 128 && d <= 256), x0, lane, wide + 1);
+        append_rows(ballot64(d > 256 && d <= 512), x0, lane, wide + (n + 1) + 1);
+        append_rows(ballot64(d > 512), x0, lane, wide + 2 * (n + 1) + 1);
     }
     add_gather(gsum, acc);
 }
 
-// Anchor work of the light sources with d+ > 64, one wave per list: lists of
-// at most kSortCap entries are sorted into rank order by a bitonic network in
-// LDS and written back; longer ones keep their order.  Writes Wu of its lists
-// only (after k_work_lanes).
-__global__ void __launch_bounds__(256) k_work_lds(int64_t n, const int4* __restrict__ rowQ,
-                                                   int32_t* __restrict__ colO, int32_t vcap,
-                                                   int2* __restrict__ packU, int2* __restrict__ packD,
-                                                   unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
-                                                   int64_t* __restrict__ acc) {
-    __shared__ uint64_t keys[4][kSortCap];
+// Anchor work of the light sources with 32 R < d+ <= 64 R (R = 16: every
+// d+ > 512), one wave per list, over the vertex list L (count at L[-1]) that
+// k_work_lanes appended; one instantiation per register class, so that the
+// shorter classes keep their occupancy.  Writes Wu of its lists.
+template <int R>
+__global__ void __launch_bounds__(256) k_work_wide(const int32_t* __restrict__ L, const int4* __restrict__ rowQ,
+                                                    int32_t* __restrict__ colO, int32_t vcap,
+                                                    int2* __restrict__ packU, int2* __restrict__ packD,
+                                                    unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
+                                                    int64_t* __restrict__ acc) {
+    static_assert(kSortCap == 64 * 16, "list classes of k_work_wide");
     const int lane = __lane_id();
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint64_t* sk = keys[wv];
-    const int64_t gw = (int64_t)blockIdx.x * 4 + wv;
-    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int32_t cnt = L[-1];
     int64_t gsum = 0;
-    for (int64_t x0 = gw * 64; x0 < n; x0 += nw * 64) {
-        const int64_t x = x0 + lane;
-        const int4 q = x < n ? rowQ[x] : make_int4(0, 0, 0, 0);
-        uint64_t todo = ballot64(q.y > 64);
-        while (todo) {
-            const int l = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const int32_t rs = __builtin_amdgcn_readlane(q.x, l);
-            const int32_t d = __builtin_amdgcn_readlane(q.y, l);
-            int64_t wu = 0;
-            if (d <= kSortCap) {
-                int G = 128;
-                while (G < d) G <<= 1;
-                constexpr int R = kSortCap / 64;
-                int32_t w[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int i = lane + 64 * r;
-                    w[r] = i < d ? colO[rs + i] : 0;
-                }
-                int32_t dg[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) dg[r] = lane + 64 * r < d ? rowQ[w[r]].z : 0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int i = lane + 64 * r;
-                    if (i < G) sk[i] = i < d ? rank_key(dg[r], w[r]) : ~0ull;
-                }
-                wave_lds_sync();
-                for (int K = 2; K <= G; K <<= 1) {
-                    for (int J = K >> 1; J > 0; J >>= 1) {
-                        for (int t = lane; t < (G >> 1); t += 64) {
-                            const int i = ((t & ~(J - 1)) << 1) | (t & (J - 1));  // bit J of i clear
-                            const uint64_t a = sk[i], b = sk[i | J];
-                            if ((i & K) == 0 ? a > b : a < b) {
-                                sk[i] = b;
-                                sk[i | J] = a;
-                            }
-                        }
-                        wave_lds_sync();
-                    }
-                }
-                for (int k = lane; k < d; k += 64) {
-                    const int32_t v = (int32_t)(uint32_t)sk[k];
-                    const int4 qv = rowQ[v];
-                    colO[rs + k] = v;
-                    pair_work(rs, d, k, v, qv, true, vcap, packU, packD, cw, wu, gsum);
-                }
-                wave_lds_sync();  // keys read before the next list overwrites them
-            } else {
-                for (int k = lane; k < d; k += 64) {
-                    const int32_t v = colO[rs + k];
-                    pair_work(rs, d, k, v, rowQ[v], false, vcap, packU, packD, cw, wu, gsum);
-                }
-            }
-            wu = wave_sum(wu);
-            if (lane == 0) Wu[x0 + l] = wu;
-        }
+    for (int32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); i < cnt;
+         i += gridDim.x * 4) {
+        const int32_t x = L[i];
+        const int4 q = rowQ[x];  // wave-uniform
+        work_wide_lists<R>(1ull, q, x, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
     }
     add_gather(gsum, acc);
 }
@@ -388,9 +534,9 @@ __device__ __forceinline__ int32_t items_of(int64_t w, int32_t len) {
     return w > 0 ? (len + kJL - 1) / kJL : 0;
 }
 
-// Length total and count of x's v-major descriptors.
+// Length total of x's v-major descriptors, and one past their last slot.
 __device__ __forceinline__ int64_t cw_len(unsigned long long c) { return (int64_t)(c & 0xFFFFFFFFull); }
-__device__ __forceinline__ int32_t cw_cnt(unsigned long long c) { return (int32_t)(c >> 32); }
+__device__ __forceinline__ int32_t cw_end(unsigned long long c) { return (int32_t)(c >> 32); }
 
 // per vertex: item counts of the two bins (wave / block anchors), statistics
 // and the model bytes of each light kernel:
@@ -400,7 +546,8 @@ __device__ __forceinline__ int32_t cw_cnt(unsigned long long c) { return (int32_
 __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __restrict__ code,
                                                    const int32_t* __restrict__ dplus, const int64_t* __restrict__ Wu,
                                                    const unsigned long long* __restrict__ cw,
-                                                   int32_t small_dmax, int32_t* __restrict__ nsm,
+                                                   const int32_t* __restrict__ rpD, int32_t small_dmax,
+                                                   int32_t* __restrict__ nsm,
                                                    int32_t* __restrict__ nlg, int32_t* __restrict__ nhg,
                                                    int64_t* __restrict__ part) {
     int64_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sources, out, wedges, probes, bytes_s, bytes_l, items_s, items_l
@@ -411,7 +558,7 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
         if (c > 0) { st[0] += 1; st[1] += c; st[2] += (int64_t)c * (c - 1) / 2; }
         const unsigned long long c2 = cw[x];
         const int64_t wu = Wu[x], wv = cw_len(c2);
-        const int32_t nv = cw_cnt(c2);
+        const int32_t nv = cw_end(c2) - rpD[x];
         const int32_t cu = items_of(wu, dp);
         const int32_t cv = items_of(wv, nv);
         const int64_t bytes = (int64_t)(cu + cv) * (8 + 4 * (int64_t)dp) + (wu > 0 ? 8 * (int64_t)dp : 0) +
@@ -454,13 +601,14 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
 // for the ranges r of x's v-major descriptors
 __global__ void k_items(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ base,
                         const int32_t* __restrict__ dplus, const int64_t* __restrict__ Wu,
-                        const unsigned long long* __restrict__ cw, int2* __restrict__ items) {
+                        const unsigned long long* __restrict__ cw, const int32_t* __restrict__ rpD,
+                        int2* __restrict__ items) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         if (cnt[x] == 0) continue;
         int32_t b = base[x];
         const int32_t cu = items_of(Wu[x], dplus[x]);
         const unsigned long long c2 = cw[x];
-        const int32_t cv = items_of(cw_len(c2), cw_cnt(c2));
+        const int32_t cv = items_of(cw_len(c2), cw_end(c2) - rpD[x]);
         for (int32_t r = 0; r < cu; ++r) items[b++] = make_int2((int32_t)x, r);
         for (int32_t r = 0; r < cv; ++r) items[b++] = make_int2(~(int32_t)x, r);
     }
@@ -832,7 +980,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         d = rpO[x + 1] - rs;
         int32_t llen;
         if (kind_u) { L = packU + rs; llen = d; }
-        else { L = packD + rpD[x]; llen = cw_cnt(cw[x]); }
+        else { const int32_t ds = rpD[x]; L = packD + ds; llen = cw_end(cw[x]) - ds; }
         const int32_t j0 = item.y * kJL;
         L += j0;
         cnt = min(kJL, llen - j0);
@@ -920,7 +1068,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         const int2* L;
         int32_t llen;
         if (kind_u) { L = packU + rs; llen = d; }
-        else { L = packD + rpD[x]; llen = cw_cnt(cw[x]); }
+        else { const int32_t ds = rpD[x]; L = packD + ds; llen = cw_end(cw[x]) - ds; }
         const int32_t j0 = item.y * kJL;
         const int32_t cnt = min(kJL, llen - j0);
         const int lg = bucket_bits(d);
@@ -1200,7 +1348,8 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     DevBuf<int32_t> rpO(n + 1, s), dplus(n, s);
     positions_at_rows(v_row, n, E2, ubits.get(), upre.get(), rpO.get(), dplus.get(), s);
     DevBuf<int32_t> colO(g->m, s);  // m' <= m
-    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), nullptr, s, E2_dev);
+    DevBuf<int2> packU(g->m, s);    // one descriptor per up entry, cleared by the compaction
+    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), nullptr, s, E2_dev, packU.get());
 
     // 3. classification; anchor work (each light source's N+(u) in rank
     //    order, one descriptor per pair); item lists
@@ -1211,23 +1360,40 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
               dminus.get());
     scan_exclusive_i32(dminus.get(), rpD.get(), n, s);  // slots of each vertex's v-major descriptors
     DevBuf<int4> rowQ(n, s);
-    TC_LAUNCH("row_q", k_row_q, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)rpO.get(),
-              (const int32_t*)code.get(), (const int32_t*)dplus.get(), degp, (const int32_t*)rpD.get(), rowQ.get());
     DevBuf<int64_t> Wu(n, s), cw(n, s);
-    fill_i64(cw.get(), 0, n, s);
+    DevBuf<int2> packD(vcap > 0 ? g->m : 1, s);  // v-major descriptors, rpD[v].. for vertex v
     unsigned long long* cwp = reinterpret_cast<unsigned long long*>(cw.get());
-    DevBuf<int2> packU(g->m, s), packD(vcap > 0 ? g->m : 1, s);
+    TC_LAUNCH("row_q", k_row_q, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)rpO.get(),
+              (const int32_t*)code.get(), (const int32_t*)dplus.get(), degp, (const int32_t*)rpD.get(), rowQ.get(),
+              cwp);
+    DevBuf<int32_t> wide(3 * (n + 1), s);  // vertices with d+ in (128, 256], (256, 512], > 512; counts first
+    for (int c = 0; c < 3; ++c) fill_i32(wide.get() + c * (n + 1), 0, 1, s);
     TC_LAUNCH("work", k_work_lanes, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int4*)rowQ.get(),
-              colO.get(), vcap, packU.get(), packD.get(), cwp, Wu.get(), acc);
-    if (g->max_deg > 64)  // bounds every d+
-        TC_LAUNCH("work_lds", k_work_lds, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int4*)rowQ.get(),
-                  colO.get(), vcap, packU.get(), packD.get(), cwp, Wu.get(), acc);
+              colO.get(), vcap, packU.get(), packD.get(), cwp, Wu.get(), wide.get(), acc);
+    // longer lists by register class, persistent grids of one round of
+    // resident blocks; max_deg bounds every d+
+    auto launch_wide = [&](auto kernel, int c, int32_t lo, const char* name, std::atomic<int>& resident) {
+        if (g->max_deg <= lo) return;
+        int r = resident.load(std::memory_order_relaxed);
+        if (!r) {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, kernel, 256, 0) != hipSuccess || r < 1) r = 1;
+            (void)hipGetLastError();
+            resident.store(r, std::memory_order_relaxed);
+        }
+        TC_LAUNCH(name, kernel, dim3((unsigned)(num_cus() * r)), dim3(256), 0, s,
+                  (const int32_t*)wide.get() + c * (n + 1) + 1, (const int4*)rowQ.get(), colO.get(), vcap,
+                  packU.get(), packD.get(), cwp, Wu.get(), acc);
+    };
+    static std::atomic<int> res_w[3];
+    launch_wide(k_work_wide<4>, 0, 128, "work_w4", res_w[0]);
+    launch_wide(k_work_wide<8>, 1, 256, "work_w8", res_w[1]);
+    launch_wide(k_work_wide<16>, 2, 512, "work_w16", res_w[2]);
     DevBuf<int32_t> nsm(n + 1, s), nlg(n + 1, s), nhg(n + 1, s);
     const unsigned cgrid = std::min<unsigned>(grid_for(n, 256), kClassifyBlocks);
     DevBuf<int64_t> cpart((size_t)cgrid * 9, s);
     TC_LAUNCH("classify", k_classify, dim3(cgrid), dim3(256), 0, s, n, (const int32_t*)code.get(),
-              (const int32_t*)dplus.get(), (const int64_t*)Wu.get(), (const unsigned long long*)cwp, cfg.small_dmax,
-              nsm.get(), nlg.get(), nhg.get(), cpart.get());
+              (const int32_t*)dplus.get(), (const int64_t*)Wu.get(), (const unsigned long long*)cwp,
+              (const int32_t*)rpD.get(), cfg.small_dmax, nsm.get(), nlg.get(), nhg.get(), cpart.get());
     DevBuf<int32_t> sbase(n + 1, s), lbase(n + 1, s), hbase(n + 1, s), hpos(n + 1, s);
     scan_exclusive_i32(nsm.get(), sbase.get(), n, s);
     scan_exclusive_i32(nlg.get(), lbase.get(), n, s);
@@ -1241,7 +1407,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         DevBuf<int2> items(items_max, s);
         TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)nsm.get(),
                   (const int32_t*)sbase.get(), (const int32_t*)dplus.get(), (const int64_t*)Wu.get(),
-                  (const unsigned long long*)cwp, items.get());
+                  (const unsigned long long*)cwp, (const int32_t*)rpD.get(), items.get());
         // a persistent grid larger than what stays resident would run its last
         // blocks in a second round: cap the blocks per CU at the resident count
         static const int resident = [] {
@@ -1261,7 +1427,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         DevBuf<int2> items(items_max, s);
         TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)cnt.get(),
                   (const int32_t*)base.get(), (const int32_t*)dplus.get(), (const int64_t*)Wu.get(),
-                  (const unsigned long long*)cwp, items.get());
+                  (const unsigned long long*)cwp, (const int32_t*)rpD.get(), items.get());
         // tab: 4 * next_pow2(d) <= 4 * dcap slots, P: kJL+1, D: kJL, flags: 4*64*kU (16-byte multiple)
         const size_t per_block = (size_t)large_block_words(dcap);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
@@ -1355,7 +1521,7 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     b += rb(8 * NW) + rb(4 * (NW + 1)) + scan_scratch_bytes(NW);  // orientation bits, prefixes
     b += rb(4 * (n + 1)) + rb(4 * n) + rb(4 * m);                  // rpO, d+, up lists
     b += 2 * rb(4 * (n + 1)) + 2 * rb(4 * n) + scan_scratch_bytes(n);  // heavy, code, d-, descriptor slots
-    b += rb(16 * n) + 2 * rb(8 * n);                               // rowQ, Wu, cw
+    b += rb(16 * n) + 2 * rb(8 * n) + rb(12 * (n + 1));            // rowQ, Wu, cw, wide-list vertices
     b += rb(8 * m) + rb(8 * (cfg.vmajor_cap > 0 ? m : 1));         // packed descriptors
     b += 7 * rb(4 * (n + 1)) + 4 * scan_scratch_bytes(n);                      // item counts and bases
     b += rb(8 * 9 * (int64_t)std::min<int64_t>((n + 255) / 256, kClassifyBlocks));  // classification partials
