@@ -631,23 +631,29 @@ __global__ void k_heavy_zero(const int32_t* __restrict__ h_dev, uint8_t* __restr
 }
 
 // m', h and the classification statistics (sums of the per-block partials;
-// the last one is a maximum).  One wave.
-__global__ void k_finish(const int32_t* mp, const int32_t* hp, const int64_t* __restrict__ part, int32_t nparts,
-                         int64_t* acc) {
-    const int lane = __lane_id();
-    const int slot[9] = {kLightSources, kLightOut, kWedges, kProbes, kBytesSmall, kBytesLarge, kItemsSmall,
-                         kItemsLarge, kDmaxLarge};
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        int64_t v = 0;
-        for (int32_t b = lane; b < nparts; b += 64) {
-            const int64_t x = part[(int64_t)b * 9 + q];
-            v = q == 8 ? (x > v ? x : v) : v + x;
-        }
-        v = q == 8 ? wave_max(v) : wave_sum(v);
-        if (lane == 0) acc[slot[q]] = v;
+// the last one is a maximum).  One block of 576 threads.
+__global__ void __launch_bounds__(576) k_finish(const int32_t* mp, const int32_t* hp,
+                                                const int64_t* __restrict__ part, int32_t nparts, int64_t* acc) {
+    // thread t folds statistic q = t % 9 of the blocks t / 9, t / 9 + 64, ..
+    // (neighbouring threads read neighbouring words); then 64 values per q
+    __shared__ int64_t red[64][9];
+    const int t = threadIdx.x;
+    const int q = t % 9, c = t / 9;
+    int64_t v = 0;
+    for (int32_t b = c; b < nparts; b += 64) {
+        const int64_t x = part[(int64_t)b * 9 + q];
+        v = q == 8 ? (x > v ? x : v) : v + x;
     }
-    if (lane == 0) {
+    red[c][q] = v;
+    __syncthreads();
+    if (t < 9) {
+        const int slot[9] = {kLightSources, kLightOut, kWedges, kProbes, kBytesSmall, kBytesLarge, kItemsSmall,
+                             kItemsLarge, kDmaxLarge};
+        int64_t r = red[0][t];
+        for (int i = 1; i < 64; ++i) r = t == 8 ? (red[i][t] > r ? red[i][t] : r) : r + red[i][t];
+        acc[slot[t]] = r;
+    }
+    if (t == 0) {
         acc[kMp] = mp[0];
         acc[kH] = hp[0];
     }
@@ -1395,10 +1401,11 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
               (const int32_t*)dplus.get(), (const int64_t*)Wu.get(), (const unsigned long long*)cwp,
               (const int32_t*)rpD.get(), cfg.small_dmax, nsm.get(), nlg.get(), nhg.get(), cpart.get());
     DevBuf<int32_t> sbase(n + 1, s), lbase(n + 1, s), hbase(n + 1, s), hpos(n + 1, s);
-    scan_exclusive_i32(nsm.get(), sbase.get(), n, s);
-    scan_exclusive_i32(nlg.get(), lbase.get(), n, s);
-    scan_exclusive_i32(nhg.get(), hbase.get(), n, s);
-    scan_exclusive_i32(heavy.get(), hpos.get(), n, s);
+    {
+        const int32_t* in[4] = {nsm.get(), nlg.get(), nhg.get(), heavy.get()};
+        int32_t* out[4] = {sbase.get(), lbase.get(), hbase.get(), hpos.get()};
+        scan_exclusive_i32_x4(in, out, n, s);
+    }
 
     // 4. light phase: three bins by anchor out-degree; each kernel is a
     //    persistent grid that reads its item count from device memory
@@ -1487,7 +1494,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         TC_LAUNCH("heavy_mfma", k_heavy_mfma, dim3((unsigned)mblocks), dim3(256), 0, s, (const uint8_t*)U.get(),
                   (const uint8_t*)UT.get(), h_dev, acc);
     }
-    TC_LAUNCH("finish", k_finish, dim3(1), dim3(64), 0, s, mp_dev, (const int32_t*)hpos.get() + n,
+    TC_LAUNCH("finish", k_finish, dim3(1), dim3(576), 0, s, mp_dev, (const int32_t*)hpos.get() + n,
               (const int64_t*)cpart.get(), (int32_t)cgrid, acc);
 }
 
@@ -1523,7 +1530,7 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     b += 2 * rb(4 * (n + 1)) + 2 * rb(4 * n) + scan_scratch_bytes(n);  // heavy, code, d-, descriptor slots
     b += rb(16 * n) + 2 * rb(8 * n) + rb(12 * (n + 1));            // rowQ, Wu, cw, wide-list vertices
     b += rb(8 * m) + rb(8 * (cfg.vmajor_cap > 0 ? m : 1));         // packed descriptors
-    b += 7 * rb(4 * (n + 1)) + 4 * scan_scratch_bytes(n);                      // item counts and bases
+    b += 7 * rb(4 * (n + 1)) + scan_x4_scratch_bytes(n);                       // item counts and bases
     b += rb(8 * 9 * (int64_t)std::min<int64_t>((n + 255) / 256, kClassifyBlocks));  // classification partials
     const int64_t items_max = 2 * n + E2 / kJL + 2;
     b += rb(8 * items_max);

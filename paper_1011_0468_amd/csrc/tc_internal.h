@@ -128,8 +128,11 @@ namespace tc {
 
 // Exclusive scan of in[0..N) into out[0..N], out[N] = total.  In-place allowed.
 void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t N, hipStream_t s);
+// four arrays of one length with the launches of one scan
+void scan_exclusive_i32_x4(const int32_t* const in[4], int32_t* const out[4], int64_t N, hipStream_t s);
 // Bytes the scratch of one scan of N elements takes (sum of its allocations).
 int64_t scan_scratch_bytes(int64_t N);
+int64_t scan_x4_scratch_bytes(int64_t N);
 void fill_i32(int32_t* p, int32_t v, int64_t N, hipStream_t s);
 void fill_i64(int64_t* p, int64_t v, int64_t N, hipStream_t s);
 void fill_u8(uint8_t* p, uint8_t v, int64_t N, hipStream_t s);
