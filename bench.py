@@ -127,6 +127,41 @@ def batched(args):
           flush=True)
 
 
+def adaptive(args):
+    """Adaptive keep probability on R-MAT scale 22: p doubles from 1/64 with 16
+    seeds per stage (median of 4 means) until two stages agree to 1%; the time
+    of the whole search, its stages, the balance point of section 3.3 and the
+    error against the exact count (measured once, outside the timed region)."""
+    import torch
+    import synth
+    import paper_1011_0468_amd as tc
+    n, s, d = synth.workload("rmat22")
+    g = tc.tc_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    T = tc.tc_count_exact(g)["triangles"]
+    p0, tol, S, G = 1 / 64, 0.01, 16, 4
+
+    def search():
+        return tc.tc_estimate_adaptive(g, p0, tol, args.seed, S, G)
+
+    for _ in range(args.warmup):
+        search()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        stages, pb = search()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    edges = sum(x["m_sum"] for x in stages)
+    print(json.dumps({"metric": "adaptive-p search time (1 MI355X) at R-MAT s22", "value": round(ms, 3), "unit": "ms",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+                      "dtype": "int32", "data": "synthetic", "edges_per_s": edges / (ms / 1e3),
+                      "p_chosen": stages[-1]["p"], "estimate": stages[-1]["estimate"], "exact": T,
+                      "rel_error": stages[-1]["estimate"] / T - 1.0, "p_balance": pb,
+                      "stages": [[x["p"], x["estimate"], x["m_sum"]] for x in stages],
+                      "config": {"workload": "rmat22", "n": n, "m": g.info()["m"], "p0": p0, "tol": tol,
+                                 "seeds_per_stage": S, "groups": G, "seed0": args.seed}}), flush=True)
+
+
 def serve(args):
     """Serving: ``--requests`` R-MAT requests (scale uniform in [10, 20], edge
     factor 16, generator seed 1000 + i) counted at p uniform in {1, .5, .1}
@@ -325,6 +360,9 @@ def main():
         return
     if args.workload == "serve":
         serve(args)
+        return
+    if args.workload == "adaptive":
+        adaptive(args)
         return
     if args.workload == "heavy":
         heavy_stress(args)

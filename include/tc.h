@@ -133,6 +133,32 @@ tc_status tc_estimate(tc_graph g, double p, const uint64_t* seeds, int32_t num_s
                       int32_t num_groups, const tc_params* prm, void* stream,
                       tc_counts* per_seed, double* per_seed_est, double* mom_est);
 
+/* One stage of tc_estimate_adaptive. */
+typedef struct {
+    double p;          /* keep probability of the stage */
+    double estimate;   /* median of means of its seeds, as tc_estimate's mom_est */
+    int64_t m_sum;     /* sum of m' over its seeds (edges counted) */
+} tc_stage;
+
+/* Adaptive keep probability: the remarks after Table 2 recommend varying p
+   and reading the estimate where it settles; section 3.3 balances the sampling
+   term pm against the counting term.  Stage k (k = 0, 1, ..) runs tc_estimate
+   with p_k = min(1, p0 * 2^k), the num_seeds seeds seed0 + k * num_seeds + i
+   (i < num_seeds, modulo 2^64) and num_groups groups.  The search stops after
+   the first stage k >= 1 whose estimate E_k is positive and satisfies
+   |E_k - E_{k-1}| <= tol * E_k (double arithmetic; an estimate of 0 never
+   counts as settled), after a stage with
+   p_k = 1 (the exact count), or after max_stages stages.  stages[max_stages]
+   (host) receives the stages run and *num_stages their number.  *p_balance
+   (may be NULL) receives min(1, (m^(1/2) ln(n) / (E tol^2))^(2/5)), the p at
+   which section 3.3's two terms balance with t = E, the last estimate, and
+   epsilon = tol (1 if E <= 0 or tol = 0).  p0 in (0, 1], tol >= 0 and
+   finite, max_stages >= 1; num_seeds and num_groups as for tc_estimate.
+   Errors as tc_estimate; stages written before an error stay valid. */
+tc_status tc_estimate_adaptive(tc_graph g, double p0, double tol, uint64_t seed0, int32_t num_seeds,
+                               int32_t num_groups, int32_t max_stages, const tc_params* prm, void* stream,
+                               tc_stage* stages, int32_t* num_stages, double* p_balance);
+
 /* Random-projection estimator (section 5.1) with Rademacher vectors: for
    l < k, x_l[i] = +1 if bit (l & 63) of
    mix64(mix64((l >> 6) << 32 | i) ^ mix64(seed ^ 0x52505F5452414345)) is 0, else -1;

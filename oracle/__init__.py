@@ -10,6 +10,7 @@ All functions take / return numpy arrays.  A normalised graph is the tuple
 ``(n, row_ptr int64[n+1], col int32[2m])`` with sorted neighbour lists.
 """
 import ctypes
+import math
 import os
 import subprocess
 
@@ -168,6 +169,44 @@ def estimate(T, p):
 def median_of_means(counts, num_groups, p):
     c = np.ascontiguousarray(counts, dtype=np.int64)
     return float(_load().or_median_of_means(_i64(c), len(c), num_groups, float(p)))
+
+
+def balance_p(m, n, t, eps):
+    """Section 3.3: the p at which the sampling term p m equals the counting
+    term m^(3/2) log n / (p^(3/2) t eps^2), i.e. (m^(1/2) ln n / (t eps^2))^(2/5),
+    capped at 1 (1 when t <= 0 or eps = 0; natural logarithm)."""
+    if t <= 0 or eps == 0:
+        return 1.0
+    return min(1.0, (math.sqrt(m) * math.log(n) / (t * (eps * eps))) ** 0.4)
+
+
+def estimate_adaptive(g, p0, tol, seed0, num_seeds, num_groups, max_stages=32):
+    """Vary p until the estimate settles (the remarks after Table 2): stage k
+    samples with p = min(1, p0 2^k) and the seeds seed0 + k num_seeds + i,
+    counts each sample exactly and takes the median of means (section 3.1
+    rescaling); the search ends after the first stage k >= 1 with E_k > 0 and
+    |E_k - E_(k-1)| <= tol E_k, after the stage at p = 1, or after
+    max_stages stages.  An estimate of 0 never counts as settled (a sample
+    without triangles says nothing about the rate).  Returns ([(p, estimate,
+    sum of m')], balance_p of the last estimate)."""
+    n, rp, col = g
+    m = len(col) // 2
+    stages = []
+    prev = 0.0
+    for k in range(max_stages):
+        p = min(1.0, math.ldexp(p0, k))
+        counts, msum = [], 0
+        for i in range(num_seeds):
+            seed = (seed0 + k * num_seeds + i) % (1 << 64)
+            gs = g if p >= 1.0 else sample(g, p, seed)
+            counts.append(count(gs))
+            msum += len(gs[2]) // 2
+        est = median_of_means(counts, num_groups, p)
+        stages.append((p, est, msum))
+        if p >= 1.0 or (k >= 1 and est > 0.0 and abs(est - prev) <= tol * est):
+            break
+        prev = est
+    return stages, balance_p(m, n, stages[-1][1], tol)
 
 
 def rp_sign(seed, l, i):

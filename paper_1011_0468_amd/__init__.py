@@ -15,9 +15,10 @@ import ctypes
 import numpy as np
 
 from . import _native
-from ._native import TcCounts, TcError, TcParams, TcRequest, TcResult, TcServerConfig, TcServerInfo, TcTuning, check
+from ._native import (TcCounts, TcError, TcParams, TcRequest, TcResult, TcServerConfig, TcServerInfo, TcStage, TcTuning,
+                      check)
 
-__all__ = ["Graph", "tc_build_csr", "tc_sample", "tc_count_exact", "tc_estimate", "tc_rp_trace",
+__all__ = ["Graph", "tc_build_csr", "tc_sample", "tc_count_exact", "tc_estimate", "tc_estimate_adaptive", "tc_rp_trace",
            "tc_graph_info", "tc_graph_read", "tc_tune_set", "tc_tune_get", "tc_autotune", "profile", "TcError",
            "Server", "tc_request_bytes"]
 
@@ -132,6 +133,20 @@ def tc_estimate(g, p, seeds, num_groups=1, heavy=(1, 1), tuned=False, stream=Non
     check(_native.load().tc_estimate(g.handle, float(p), arr, S, int(num_groups), ctypes.byref(prm),
                                      _stream_ptr(stream), per, ests, ctypes.byref(mom)))
     return [c.as_dict() for c in per], list(ests), mom.value
+
+
+def tc_estimate_adaptive(g, p0, tol, seed0=0, num_seeds=8, num_groups=4, max_stages=32, heavy=(1, 1),
+                         tuned=False, stream=None):
+    """Stages of the adaptive keep probability (list of dicts p, estimate,
+    m_sum; the last one is the answer) and the section 3.3 balance point."""
+    st = (TcStage * int(max_stages))()
+    ns = ctypes.c_int32(0)
+    pb = ctypes.c_double(0.0)
+    prm = _params(heavy, tuned)
+    check(_native.load().tc_estimate_adaptive(g.handle, float(p0), float(tol), int(seed0) & (2 ** 64 - 1),
+                                              int(num_seeds), int(num_groups), int(max_stages), ctypes.byref(prm),
+                                              _stream_ptr(stream), st, ctypes.byref(ns), ctypes.byref(pb)))
+    return [st[i].as_dict() for i in range(ns.value)], pb.value
 
 
 def tc_rp_trace(g, k, seed, stream=None):

@@ -505,6 +505,30 @@ static void count_batch(const tc_graph_s* g, int sampled, uint64_t thr, const ui
     for (int32_t i = 0; i < S; ++i) counts_from_slots(h.data() + (size_t)i * kCountSlots, &res[(size_t)i]);
 }
 
+// Median of the group means of the counts (groups of consecutive seeds; for
+// an even number of groups the two middle group sums are added and divided
+// once), rescaled by 1/p^3 (section 3.1), in the order of operations the
+// oracle follows.
+static double median_of_means(const std::vector<tc_counts>& res, int32_t num_groups, double p) {
+    const int32_t S = (int32_t)res.size();
+    const int32_t per = S / num_groups;
+    std::vector<int64_t> sums((size_t)num_groups, 0);
+    for (int32_t gi = 0; gi < num_groups; ++gi)
+        for (int32_t i = 0; i < per; ++i) sums[(size_t)gi] += res[(size_t)(gi * per + i)].triangles;
+    std::sort(sums.begin(), sums.end());
+    volatile double p2 = p * p;
+    volatile double p3 = p2 * p;
+    if (num_groups % 2 == 0) {
+        const int64_t M = sums[(size_t)(num_groups / 2 - 1)] + sums[(size_t)(num_groups / 2)];
+        volatile double den = 2.0 * (double)per;
+        den = den * p3;
+        return (double)M / den;
+    }
+    volatile double den = (double)per;
+    den = den * p3;
+    return (double)sums[(size_t)((num_groups - 1) / 2)] / den;
+}
+
 tc_status tc_estimate(tc_graph g, double p, const uint64_t* seeds, int32_t num_seeds, int32_t num_groups,
                       const tc_params* prm, void* stream, tc_counts* per_seed, double* per_seed_est,
                       double* mom_est) {
@@ -525,24 +549,49 @@ tc_status tc_estimate(tc_graph g, double p, const uint64_t* seeds, int32_t num_s
             for (int32_t i = 0; i < num_seeds; ++i) per_seed[i] = res[(size_t)i];
         if (per_seed_est)
             for (int32_t i = 0; i < num_seeds; ++i) per_seed_est[i] = rescale(res[(size_t)i].triangles, p);
-        if (mom_est) {
-            const int32_t per = num_seeds / num_groups;
-            std::vector<int64_t> sums((size_t)num_groups, 0);
-            for (int32_t gi = 0; gi < num_groups; ++gi)
-                for (int32_t i = 0; i < per; ++i) sums[(size_t)gi] += res[(size_t)(gi * per + i)].triangles;
-            std::sort(sums.begin(), sums.end());
-            volatile double p2 = p * p;
-            volatile double p3 = p2 * p;
-            if (num_groups % 2 == 0) {
-                const int64_t M = sums[(size_t)(num_groups / 2 - 1)] + sums[(size_t)(num_groups / 2)];
-                volatile double den = 2.0 * (double)per;
-                den = den * p3;
-                *mom_est = (double)M / den;
-            } else {
-                volatile double den = (double)per;
-                den = den * p3;
-                *mom_est = (double)sums[(size_t)((num_groups - 1) / 2)] / den;
+        if (mom_est) *mom_est = median_of_means(res, num_groups, p);
+    });
+}
+
+tc_status tc_estimate_adaptive(tc_graph g, double p0, double tol, uint64_t seed0, int32_t num_seeds,
+                               int32_t num_groups, int32_t max_stages, const tc_params* prm, void* stream,
+                               tc_stage* stages, int32_t* num_stages, double* p_balance) {
+    if (num_stages) *num_stages = 0;
+    return guarded([&] {
+        if (!g || !stages || !num_stages) fail(TC_ERR_INVALID, "graph, stages or num_stages is NULL");
+        if (!p_valid(p0)) fail(TC_ERR_INVALID, "p0 must be finite and in (0, 1]");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(TC_ERR_INVALID, "tol must be finite and >= 0");
+        if (max_stages < 1) fail(TC_ERR_INVALID, "max_stages must be >= 1");
+        if (num_seeds < 1) fail(TC_ERR_INVALID, "need at least one seed");
+        if (num_groups < 1 || num_groups > num_seeds || num_seeds % num_groups)
+            fail(TC_ERR_INVALID, "num_groups must divide num_seeds");
+        std::vector<tc_counts> res;
+        std::vector<uint64_t> salts((size_t)num_seeds);
+        double prev = 0.0;
+        for (int32_t k = 0; k < max_stages; ++k) {
+            const double p = std::min(1.0, std::ldexp(p0, k));  // exact: a power-of-two scaling
+            const int sampled = p < 1.0 ? 1 : 0;
+            const CountConfig cfg = config_from(prm, g, sampled, p);
+            for (int32_t i = 0; i < num_seeds; ++i)
+                salts[(size_t)i] = sample_salt(seed0 + (uint64_t)k * (uint64_t)num_seeds + (uint64_t)i);
+            count_batch(g, sampled, keep_threshold(p), salts.data(), num_seeds, cfg, (hipStream_t)stream, res);
+            tc_stage st{};
+            st.p = p;
+            st.estimate = median_of_means(res, num_groups, p);
+            for (const tc_counts& c : res) st.m_sum += c.m;
+            stages[k] = st;
+            *num_stages = k + 1;
+            if (p >= 1.0 || (k >= 1 && st.estimate > 0.0 && std::fabs(st.estimate - prev) <= tol * st.estimate)) break;
+            prev = st.estimate;
+        }
+        if (p_balance) {
+            const double E = stages[*num_stages - 1].estimate;
+            double pb = 1.0;
+            if (E > 0.0 && tol > 0.0) {
+                const double x = std::sqrt((double)g->m) * std::log((double)g->n) / (E * (tol * tol));
+                pb = std::min(1.0, std::pow(x, 0.4));
             }
+            *p_balance = pb;
         }
     });
 }
