@@ -125,15 +125,15 @@ __device__ __forceinline__ bool is_heavy(int64_t deg, int64_t m, int32_t a, int3
 }
 
 // Orders one wave's shared-table writes before its later reads.  LDS
-// operations of a wave complete in order, so for tables in LDS only the
-// compiler must be kept from moving accesses across (fences) and outstanding
-// LDS results are drained (lgkmcnt); global loads stay in flight.  Tables in
-// global scratch (GLOBAL) need every outstanding access drained.
+// operations of a wave are executed and complete in issue order, so for
+// tables in LDS only the compiler must be kept from moving accesses across
+// (fences and the wave barrier); no wait is needed, and global loads stay in
+// flight.  Tables in global scratch (GLOBAL) need every outstanding access
+// drained.
 template <bool GLOBAL>
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     if (GLOBAL) __builtin_amdgcn_s_waitcnt(0);
-    else __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt unrestricted
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
