@@ -159,6 +159,34 @@ tc_status tc_estimate_adaptive(tc_graph g, double p0, double tol, uint64_t seed0
                                int32_t num_groups, int32_t max_stages, const tc_params* prm, void* stream,
                                tc_stage* stages, int32_t* num_stages, double* p_balance);
 
+/* Triple sampling (section 3.2, "Triple Sampling"; the Simple and Hybrid
+   columns of Table 2) on g, or on g sparsified with (p, sample_seed) as
+   tc_sample does when p < 1.  The candidate set U of the counted graph, in
+   order: vertices u ascending; a vertex of the wedge kind gives its pairs of
+   neighbour positions a < b in colex order ((0,1), (0,2), (1,2), (0,3), ..),
+   the triple (N(u)[a], u, N(u)[b]), closed iff N(u)[a] and N(u)[b] are
+   adjacent; a vertex of the extension kind gives, for each neighbour
+   position a (v = N(u)[a]) and each neighbour position j of v
+   (w = N(v)[j]), the triple (u, v, w), closed iff w != u and w is adjacent
+   to u.  hybrid = 0 (Simple): every vertex is of the wedge kind; hybrid = 1:
+   the extension kind iff deg^2 > m (degree and m of the counted graph).
+   Sample i < num_samples is triple r_i = floor(h_i |U| / 2^64) with
+   h_i = mix64(mix64(i) ^ mix64(triple_seed ^ 0x54435F545249504C)); a closed
+   sample weighs 60 / (3 + its extension-kind vertices), so each triangle's
+   appearances in U weigh 60 in all.  estimate =
+   ((double)|U| * (double)weight_sum) / (60.0 * (double)num_samples), then
+   divided by (p*p)*p.  num_samples >= 1; errors as tc_sample. */
+typedef struct {
+    int64_t size;        /* |U| */
+    int64_t weight_sum;  /* sum of the closed samples' weights */
+    int64_t closed;      /* closed samples */
+    int64_t m;           /* edges of the counted graph */
+    double estimate;     /* of the triangle count of g */
+} tc_triple_result;
+
+tc_status tc_triple_estimate(tc_graph g, double p, uint64_t sample_seed, int32_t hybrid, int64_t num_samples,
+                             uint64_t triple_seed, void* stream, tc_triple_result* out);
+
 /* Random-projection estimator (section 5.1) with Rademacher vectors: for
    l < k, x_l[i] = +1 if bit (l & 63) of
    mix64(mix64((l >> 6) << 32 | i) ^ mix64(seed ^ 0x52505F5452414345)) is 0, else -1;

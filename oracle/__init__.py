@@ -71,6 +71,16 @@ def _load():
     L.or_rp_trace.restype = ctypes.c_int
     L.or_rp_q.argtypes = [i64, P(i64), P(i32), i64, u64]
     L.or_rp_q.restype = i64
+    L.or_triples_size.argtypes = [i64, P(i64), P(i32), ctypes.c_int, P(i64)]
+    L.or_triples_size.restype = i64
+    L.or_triple_at.argtypes = [i64, P(i64), P(i32), ctypes.c_int, P(i64), i64, P(i32), P(i32), P(i32)]
+    L.or_triple_at.restype = i64
+    L.or_triple_index.argtypes = [u64, i64, i64]
+    L.or_triple_index.restype = i64
+    L.or_triple_sample.argtypes = [i64, P(i64), P(i32), ctypes.c_int, i64, u64, P(i64)]
+    L.or_triple_sample.restype = ctypes.c_int
+    L.or_triple_estimate.argtypes = [i64, i64, i64, dbl]
+    L.or_triple_estimate.restype = dbl
     _lib = L
     return L
 
@@ -169,6 +179,41 @@ def estimate(T, p):
 def median_of_means(counts, num_groups, p):
     c = np.ascontiguousarray(counts, dtype=np.int64)
     return float(_load().or_median_of_means(_i64(c), len(c), num_groups, float(p)))
+
+
+def triples_size(g, hybrid, with_prefix=False):
+    """|U| of section 3.2's triple sampling (wedges; extensions for deg^2 > m
+    when hybrid), and the start of each vertex's triples if with_prefix."""
+    n, rp, col = g
+    pre = np.zeros(n + 1, np.int64)
+    size = int(_load().or_triples_size(n, _i64(rp), _i32(col), 1 if hybrid else 0, _i64(pre)))
+    return (size, pre) if with_prefix else size
+
+
+def triple_at(g, hybrid, prefix, r):
+    """((x, y, z), weight if closed else 0) of triple r of U."""
+    n, rp, col = g
+    x, y, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    w = _load().or_triple_at(n, _i64(rp), _i32(col), 1 if hybrid else 0, _i64(prefix), int(r), ctypes.byref(x),
+                             ctypes.byref(y), ctypes.byref(z))
+    return (x.value, y.value, z.value), int(w)
+
+
+def triple_index(seed, i, size):
+    return int(_load().or_triple_index(seed & (2 ** 64 - 1), i, size))
+
+
+def triple_sample(g, hybrid, s, seed):
+    """(|U|, weight sum, closed samples) of s samples of U."""
+    n, rp, col = g
+    out = np.zeros(3, np.int64)
+    if _load().or_triple_sample(n, _i64(rp), _i32(col), 1 if hybrid else 0, s, seed & (2 ** 64 - 1), _i64(out)):
+        raise MemoryError("oracle triples")
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def triple_estimate(size, wsum, s, p=1.0):
+    return float(_load().or_triple_estimate(size, wsum, s, float(p)))
 
 
 def balance_p(m, n, t, eps):

@@ -364,3 +364,140 @@ int64_t or_rp_q(int64_t n, const int64_t* row_ptr, const int32_t* col, int64_t l
     free(x);
     return q;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Triple sampling (section 3.2, "Triple Sampling"; the Simple and Hybrid    */
+/* columns of Table 2).                                                       */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * The candidate set U, in a fixed order: vertices u ascending; a vertex of
+ * the wedge kind contributes its pairs of neighbour positions (a, b), a < b,
+ * in colex order ((0,1), (0,2), (1,2), (0,3), ...), the triple
+ * (N(u)[a], u, N(u)[b]); a vertex of the extension kind contributes, for each
+ * neighbour position a (v = N(u)[a]) in order, each neighbour position j of v
+ * (w = N(v)[j]), the triple (u, v, w).  Simple: every vertex is of the wedge
+ * kind.  Hybrid: a vertex x is of the extension kind iff deg(x)^2 > m (the
+ * degree split of section 3.2).  A wedge is closed iff its two ends are
+ * adjacent; an extension (u, v, w) iff w != u and w is adjacent to u.  A
+ * triangle appears once per wedge-kind vertex and twice per extension-kind
+ * vertex, so a closed sample weighs 60 / (3 + its extension-kind vertices)
+ * and the weights of one triangle's appearances sum to 60.
+ */
+static int ext_kind(int hybrid, int64_t deg, int64_t m) { return hybrid && deg * deg > m; }
+
+static int adjacent(const int64_t* row_ptr, const int32_t* col, int32_t x, int32_t y) {
+    int64_t lo = row_ptr[x], hi = row_ptr[x + 1];  /* sorted list of x: binary search for y */
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (col[mid] < y) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < row_ptr[x + 1] && col[lo] == y;
+}
+
+/* number of triples of vertex u */
+static int64_t triples_of(int hybrid, const int64_t* row_ptr, const int32_t* col, int64_t m, int64_t u) {
+    const int64_t d = row_ptr[u + 1] - row_ptr[u];
+    if (!ext_kind(hybrid, d, m)) return d * (d - 1) / 2;
+    int64_t c = 0;
+    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) c += row_ptr[col[e] + 1] - row_ptr[col[e]];
+    return c;
+}
+
+/* |U|; prefix (n+1 entries, may be NULL) receives the start of each vertex's triples */
+int64_t or_triples_size(int64_t n, const int64_t* row_ptr, const int32_t* col, int hybrid, int64_t* prefix) {
+    const int64_t m = row_ptr[n] / 2;
+    int64_t tot = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        if (prefix) prefix[u] = tot;
+        tot += triples_of(hybrid, row_ptr, col, m, u);
+    }
+    if (prefix) prefix[n] = tot;
+    return tot;
+}
+
+/*
+ * Triple r of U (0 <= r < |U|, prefix from or_triples_size): *x, *y, *z get
+ * its vertices in the order of the definition above; returns its weight
+ * (60 / (3 + extension-kind vertices)) if it is closed, else 0.
+ */
+int64_t or_triple_at(int64_t n, const int64_t* row_ptr, const int32_t* col, int hybrid, const int64_t* prefix,
+                     int64_t r, int32_t* x, int32_t* y, int32_t* z) {
+    const int64_t m = row_ptr[n] / 2;
+    int64_t lo = 0, hi = n - 1;  /* the vertex u with prefix[u] <= r < prefix[u+1] */
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (prefix[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t u = lo, k = r - prefix[u];
+    const int64_t d = row_ptr[u + 1] - row_ptr[u];
+    int closed;
+    if (!ext_kind(hybrid, d, m)) {
+        int64_t b = 1;  /* the largest b with b (b - 1) / 2 <= k */
+        while ((b + 1) * b / 2 <= k) ++b;
+        const int64_t a = k - b * (b - 1) / 2;
+        *x = col[row_ptr[u] + a];
+        *y = (int32_t)u;
+        *z = col[row_ptr[u] + b];
+        closed = adjacent(row_ptr, col, *x, *z);
+    } else {
+        int64_t e = row_ptr[u], acc = 0;  /* the neighbour position a holding k */
+        while (acc + (row_ptr[col[e] + 1] - row_ptr[col[e]]) <= k) {
+            acc += row_ptr[col[e] + 1] - row_ptr[col[e]];
+            ++e;
+        }
+        const int32_t v = col[e];
+        *x = (int32_t)u;
+        *y = v;
+        *z = col[row_ptr[v] + (k - acc)];
+        closed = *z != (int32_t)u && adjacent(row_ptr, col, (int32_t)u, *z);
+    }
+    if (!closed) return 0;
+    const int ne = ext_kind(hybrid, row_ptr[*x + 1] - row_ptr[*x], m) +
+                   ext_kind(hybrid, row_ptr[*y + 1] - row_ptr[*y], m) +
+                   ext_kind(hybrid, row_ptr[*z + 1] - row_ptr[*z], m);
+    return 60 / (3 + ne);
+}
+
+/* index of sample i under seed: the high 64 bits of h * size, h a 64-bit hash of (seed, i) */
+int64_t or_triple_index(uint64_t seed, int64_t i, int64_t size) {
+    const uint64_t salt = or_mix64(seed ^ 0x54435F545249504CULL);  /* "TC_TRIPL" */
+    const uint64_t h = or_mix64(or_mix64((uint64_t)i) ^ salt);
+    return (int64_t)(((unsigned __int128)h * (uint64_t)size) >> 64);
+}
+
+/*
+ * s samples of U with replacement: out[0] = |U|, out[1] = sum of the weights
+ * of the closed samples, out[2] = closed samples.  Returns 0, or 2 on
+ * allocation failure.  The estimate of t is |U| out[1] / (60 s).
+ */
+int or_triple_sample(int64_t n, const int64_t* row_ptr, const int32_t* col, int hybrid, int64_t s,
+                     uint64_t seed, int64_t* out) {
+    int64_t* prefix = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (!prefix) return 2;
+    const int64_t size = or_triples_size(n, row_ptr, col, hybrid, prefix);
+    int64_t wsum = 0, closed = 0;
+    for (int64_t i = 0; size > 0 && i < s; ++i) {
+        int32_t x, y, z;
+        const int64_t w = or_triple_at(n, row_ptr, col, hybrid, prefix, or_triple_index(seed, i, size), &x, &y, &z);
+        wsum += w;
+        closed += w > 0;
+    }
+    free(prefix);
+    out[0] = size;
+    out[1] = wsum;
+    out[2] = closed;
+    return 0;
+}
+
+/* |U| out[1] / (60 s), then rescaled by 1/p^3 as or_estimate does */
+double or_triple_estimate(int64_t size, int64_t wsum, int64_t s, double p) {
+    volatile double num = (double)size * (double)wsum;
+    volatile double den = 60.0 * (double)s;
+    volatile double t = num / den;
+    volatile double p2 = p * p;
+    volatile double p3 = p2 * p;
+    return t / p3;
+}

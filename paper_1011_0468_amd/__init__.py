@@ -15,10 +15,10 @@ import ctypes
 import numpy as np
 
 from . import _native
-from ._native import (TcCounts, TcError, TcParams, TcRequest, TcResult, TcServerConfig, TcServerInfo, TcStage, TcTuning,
+from ._native import (TcCounts, TcError, TcParams, TcRequest, TcResult, TcServerConfig, TcServerInfo, TcStage, TcTripleResult, TcTuning,
                       check)
 
-__all__ = ["Graph", "tc_build_csr", "tc_sample", "tc_count_exact", "tc_estimate", "tc_estimate_adaptive", "tc_rp_trace",
+__all__ = ["Graph", "tc_build_csr", "tc_sample", "tc_count_exact", "tc_estimate", "tc_estimate_adaptive", "tc_triple_estimate", "tc_rp_trace",
            "tc_graph_info", "tc_graph_read", "tc_tune_set", "tc_tune_get", "tc_autotune", "profile", "TcError",
            "Server", "tc_request_bytes"]
 
@@ -147,6 +147,16 @@ def tc_estimate_adaptive(g, p0, tol, seed0=0, num_seeds=8, num_groups=4, max_sta
                                               int(num_seeds), int(num_groups), int(max_stages), ctypes.byref(prm),
                                               _stream_ptr(stream), st, ctypes.byref(ns), ctypes.byref(pb)))
     return [st[i].as_dict() for i in range(ns.value)], pb.value
+
+
+def tc_triple_estimate(g, p, num_samples, hybrid=False, sample_seed=0, triple_seed=0, stream=None):
+    """Triple sampling (Simple or Hybrid) on g or its (p, sample_seed) sample:
+    dict(size, weight_sum, closed, m, estimate)."""
+    r = TcTripleResult()
+    check(_native.load().tc_triple_estimate(g.handle, float(p), int(sample_seed) & (2 ** 64 - 1), 1 if hybrid else 0,
+                                            int(num_samples), int(triple_seed) & (2 ** 64 - 1), _stream_ptr(stream),
+                                            ctypes.byref(r)))
+    return r.as_dict()
 
 
 def tc_rp_trace(g, k, seed, stream=None):

@@ -596,6 +596,38 @@ tc_status tc_estimate_adaptive(tc_graph g, double p0, double tol, uint64_t seed0
     });
 }
 
+tc_status tc_triple_estimate(tc_graph g, double p, uint64_t sample_seed, int32_t hybrid, int64_t num_samples,
+                             uint64_t triple_seed, void* stream, tc_triple_result* out) {
+    return guarded([&] {
+        if (!g || !out) fail(TC_ERR_INVALID, "graph or output is NULL");
+        if (!p_valid(p)) fail(TC_ERR_INVALID, "p must be finite and in (0, 1]");
+        if (hybrid != 0 && hybrid != 1) fail(TC_ERR_INVALID, "hybrid must be 0 or 1");
+        if (num_samples < 1) fail(TC_ERR_INVALID, "need at least one sample");
+        hipStream_t s = (hipStream_t)stream;
+        tc_graph gs = g;
+        if (p < 1.0) {
+            const tc_status st = tc_sample(g, p, sample_seed, stream, &gs);
+            if (st != TC_OK) fail(st, tc_last_error());
+        }
+        tc_triple_result r{};
+        try {
+            triple_sample(gs, hybrid, num_samples, triple_seed, s, &r.size, &r.weight_sum, &r.closed);
+        } catch (...) {
+            if (gs != g) tc_graph_free(gs);
+            throw;
+        }
+        r.m = gs->m;
+        if (gs != g) tc_graph_free(gs);
+        volatile double num = (double)r.size * (double)r.weight_sum;
+        volatile double den = 60.0 * (double)num_samples;
+        volatile double t = num / den;
+        volatile double p2 = p * p;
+        volatile double p3 = p2 * p;
+        r.estimate = t / p3;
+        *out = r;
+    });
+}
+
 tc_status tc_rp_trace(tc_graph g, int32_t k, uint64_t seed, void* stream, int64_t* q, double* tri_est) {
     return guarded([&] {
         if (!g || !q) fail(TC_ERR_INVALID, "graph or q is NULL");
