@@ -135,10 +135,9 @@ int64_t scan_scratch_bytes(int64_t N);
 int64_t scan_x4_scratch_bytes(int64_t N);
 
 // Triple sampling (tc_triple.hip): |U|, the weight sum and the closed
-// samples of num_samples samples of g's candidate triples; device bytes.
+// samples of num_samples samples of g's candidate triples.
 void triple_sample(const tc_graph_s* g, int hybrid, int64_t num_samples, uint64_t seed, hipStream_t s,
                    int64_t* size, int64_t* wsum, int64_t* closed);
-int64_t triple_bytes(int64_t n, int64_t m);
 void fill_i32(int32_t* p, int32_t v, int64_t N, hipStream_t s);
 void fill_i64(int64_t* p, int64_t v, int64_t N, hipStream_t s);
 void fill_u8(uint8_t* p, uint8_t v, int64_t N, hipStream_t s);

@@ -118,11 +118,6 @@ void scan64(const int64_t* in, int64_t* out, int64_t N, hipStream_t s) {
     TC_LAUNCH("tri_scan", k_scan64_fin, dim3((unsigned)g), dim3(256), 0, s, out, N, (const int64_t*)bs.get(), nb);
 }
 
-int64_t scan64_bytes(int64_t N) {
-    const int64_t nb = N > 0 ? (N + kTile64 - 1) / kTile64 : 1;
-    return region_bytes(8 * (nb + 1)) + (nb > 1 ? scan64_bytes(nb) : 0);
-}
-
 // y in the sorted list of x
 __device__ __forceinline__ bool in_list(const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t x,
                                         int32_t y) {
@@ -203,11 +198,6 @@ __global__ void __launch_bounds__(256) k_tri_sample(int64_t s, uint64_t salt, in
 }
 
 }  // namespace
-
-int64_t triple_bytes(int64_t n, int64_t m) {
-    auto rb = region_bytes;
-    return rb(8 * (n + 1)) * 2 + rb(8 * (2 * m > 0 ? 2 * m : 1)) + rb(16) + scan64_bytes(n);
-}
 
 void triple_sample(const tc_graph_s* g, int hybrid, int64_t num_samples, uint64_t seed, hipStream_t s,
                    int64_t* size, int64_t* wsum, int64_t* closed) {
