@@ -60,15 +60,34 @@ constexpr int kU = 4;
 // orientation
 // ---------------------------------------------------------------------------
 
+// A byte that orders degrees: the degree itself below 16, above it 8 steps
+// per octave (exponent and the three bits after the leading one), so
+// class(d) < class(d') implies d < d', and equal classes below 16 mean equal
+// degrees.  At most 16 + 8 * 26 + 7 = 231.
+__device__ __forceinline__ uint32_t deg_class(int32_t d) {
+    if (d < 16) return d > 0 ? (uint32_t)d : 0u;
+    const int e = 31 - __builtin_clz((uint32_t)d);  // >= 4
+    return 16u + 8u * (uint32_t)(e - 4) + (((uint32_t)d >> (e - 3)) & 7u);
+}
+
+__global__ void k_deg_class(int64_t n, const int32_t* __restrict__ degp, uint8_t* __restrict__ cls) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        cls[x] = (uint8_t)deg_class(degp[x]);
+}
+
 // Per CSR entry (u, v) of a kept edge: "up" if (deg u, u) < (deg v, v).  Each
 // kept undirected edge has exactly one up entry, in the row of its
-// lower-ranked end.  E2 bounds the buffers; E2_dev (if not null) holds the
+// lower-ranked end.  The random per-neighbour lookup reads the degree class
+// (one byte per vertex, cache-resident), and only ties of classes above 15
+// (about 7% of R-MAT's entries) read the exact degrees; the entry streams
+// bypass the cache.  E2 bounds the buffers; E2_dev (if not null) holds the
 // number of valid entries, which may be smaller (a compacted sample in buffers
 // sized for the full graph): words past it get zero bits.  Each wave takes 4
 // words (256 entries) per step and issues all their loads before the first
-// use, the degree gathers likewise.
+// use, the class gathers likewise.
 __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__ src, const int32_t* __restrict__ col,
                                                       int64_t E2, const int32_t* __restrict__ E2_dev,
+                                                      const uint8_t* __restrict__ cls,
                                                       const int32_t* __restrict__ degp, uint64_t* __restrict__ ubits,
                                                       int32_t* __restrict__ ucnt) {
     const int lane = __lane_id();
@@ -85,19 +104,24 @@ __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__
             const int64_t e = (w0 + k) * 64 + lane;
             const int64_t ec = e < last ? e : last;  // loads stay inside the buffers
             in[k] = e < valid;
-            const int32_t a = src[ec], c = col[ec];
+            const int32_t a = __builtin_nontemporal_load(src + ec), c = __builtin_nontemporal_load(col + ec);
             u[k] = in[k] ? a : 0;  // vertex 0 exists whenever a count runs
             v[k] = in[k] ? c : 0;
         }
-        int32_t du[4], dv[4];
+        uint32_t cu[4], cv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            du[k] = degp[u[k]];
-            dv[k] = degp[v[k]];
+            cu[k] = cls[u[k]];
+            cv[k] = cls[v[k]];
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const bool up = in[k] && rank_below(du[k], u[k], dv[k], v[k]);
+            bool below = cu[k] < cv[k];
+            if (cu[k] == cv[k]) {
+                if (cu[k] < 16) below = u[k] < v[k];  // equal degrees
+                else below = rank_below(degp[u[k]], u[k], degp[v[k]], v[k]);
+            }
+            const bool up = in[k] && below;
             const uint64_t bu = ballot64(up);
             if (lane == k && w0 + k < NW) {
                 ubits[w0 + k] = bu;
@@ -1347,8 +1371,10 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     // 2. orientation by (deg, id): compacted up lists N+(x), in CSR order
     DevBuf<uint64_t> ubits(NW, s);
     DevBuf<int32_t> upre(NW + 1, s);
-    TC_LAUNCH("orient_bits", k_orient_bits, dim3(grid_for(NW, 16)), dim3(256), 0, s, v_src, v_col, E2, E2_dev, degp,
-              ubits.get(), upre.get());
+    DevBuf<uint8_t> cls(n, s);
+    TC_LAUNCH("deg_class", k_deg_class, dim3(grid_for(n, 256)), dim3(256), 0, s, n, degp, cls.get());
+    TC_LAUNCH("orient_bits", k_orient_bits, dim3(grid_for(NW, 16)), dim3(256), 0, s, v_src, v_col, E2, E2_dev,
+              (const uint8_t*)cls.get(), degp, ubits.get(), upre.get());
     scan_exclusive_i32(upre.get(), upre.get(), NW, s);
     const int32_t* mp_dev = upre.get() + NW;  // number of up entries = m'
     DevBuf<int32_t> rpO(n + 1, s), dplus(n, s);
@@ -1525,7 +1551,7 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     const int64_t NW = (E2 + 63) / 64;
     if (sampled)
         b += rb(8 * NW) + rb(4 * (NW + 1)) + rb(4 * (n + 1)) + rb(4 * n) + 2 * rb(4 * E2) + scan_scratch_bytes(NW);
-    b += rb(8 * NW) + rb(4 * (NW + 1)) + scan_scratch_bytes(NW);  // orientation bits, prefixes
+    b += rb(n) + rb(8 * NW) + rb(4 * (NW + 1)) + scan_scratch_bytes(NW);  // degree classes, orientation bits
     b += rb(4 * (n + 1)) + rb(4 * n) + rb(4 * m);                  // rpO, d+, up lists
     b += 2 * rb(4 * (n + 1)) + 2 * rb(4 * n) + scan_scratch_bytes(n);  // heavy, code, d-, descriptor slots
     b += rb(16 * n) + 2 * rb(8 * n) + rb(12 * (n + 1));            // rowQ, Wu, cw, wide-list vertices
