@@ -41,9 +41,11 @@ def _light_model_bytes(c, large):
 
 
 def _source_sha():
+    """Hash of the sources the counting kernels are compiled from."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1011_0468_amd", "csrc", "tc_count.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("tc_count.hip", "tc_device.h"):
+        with open(os.path.join(ROOT, "paper_1011_0468_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -27,6 +27,20 @@ __device__ __forceinline__ T wave_inclusive_sum(T v) {
     return v;
 }
 
+// The same for 32-bit integers with DPP lane moves (no LDS crossbar round
+// trips): prefixes within each row of 16 lanes by shifts of 1, 2, 4 and 8,
+// then the last lane of row 0 is added to row 1 and that of row 2 to row 3,
+// and the last lane of row 1 to rows 2 and 3.  Whole wave.
+__device__ __forceinline__ int32_t wave_inclusive_sum(int32_t v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
