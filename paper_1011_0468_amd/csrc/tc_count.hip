@@ -645,14 +645,6 @@ __global__ void k_heavy_list(int64_t n, const int32_t* __restrict__ heavy, const
 }
 
 // zero the first heavy_pad(h)^2 bytes of U and UT (h from device)
-__global__ void k_heavy_zero(const int32_t* __restrict__ h_dev, uint8_t* __restrict__ U, uint8_t* __restrict__ UT) {
-    const int64_t hp = heavy_pad(h_dev[0]);
-    const int64_t nw = hp * hp / 16;  // 16-byte words (hp is a multiple of 128)
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (int64_t)gridDim.x * blockDim.x) {
-        reinterpret_cast<int4*>(U)[i] = make_int4(0, 0, 0, 0);
-        reinterpret_cast<int4*>(UT)[i] = make_int4(0, 0, 0, 0);
-    }
-}
 
 // m', h and the classification statistics (sums of the per-block partials;
 // the last one is a maximum).  One block of 576 threads.
@@ -1163,19 +1155,60 @@ __global__ void k_heavy_place(const int32_t* __restrict__ hlist, const int32_t* 
 }
 
 // U[i][j] = 1 and UT[j][i] = 1 for every oriented edge between heavy ranks i < j
-__global__ void __launch_bounds__(256) k_heavy_pack(const int32_t* __restrict__ horder, const int32_t* __restrict__ h_dev,
+// Rows of U: row i holds 1 at the ranks j > i of the heavy out-neighbours of
+// the vertex of rank i (its N+ list: every vertex above a heavy one is heavy),
+// rows h..hp-1 are zero.  Persistent blocks take rows with a static stride;
+// a row is built in LDS 16 KB of columns at a time and written whole, so U
+// needs no separate clearing.
+constexpr int kRowChunk = 16384;
+__global__ void __launch_bounds__(256) k_heavy_rows(const int32_t* __restrict__ horder,
+                                                     const int32_t* __restrict__ h_dev,
                                                      const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
-                                                     const int32_t* __restrict__ hidx, uint8_t* __restrict__ U,
-                                                     uint8_t* __restrict__ UT) {
+                                                     const int32_t* __restrict__ hidx, uint8_t* __restrict__ U) {
+    __shared__ __attribute__((aligned(16))) uint8_t row[kRowChunk];
     const int32_t h = h_dev[0];
     const int64_t hp = heavy_pad(h);
-    const int i = blockIdx.x;
-    if (i >= h) return;
-    const int32_t x = horder[i];
-    for (int32_t e = rpO[x] + threadIdx.x; e < rpO[x + 1]; e += 256) {
-        const int32_t j = hidx[colO[e]];
-        U[(int64_t)i * hp + j] = 1;
-        UT[(int64_t)j * hp + i] = 1;
+    for (int64_t i = blockIdx.x; i < hp; i += gridDim.x) {
+        const int32_t b = i < h ? rpO[horder[i]] : 0;
+        const int32_t e = i < h ? rpO[horder[i] + 1] : 0;
+        for (int64_t c0 = 0; c0 < hp; c0 += kRowChunk) {
+            const int32_t w = (int32_t)min<int64_t>(kRowChunk, hp - c0);  // a multiple of 128
+            for (int32_t k = threadIdx.x; k < w / 16; k += 256) reinterpret_cast<int4*>(row)[k] = make_int4(0, 0, 0, 0);
+            __syncthreads();
+            for (int32_t q = b + threadIdx.x; q < e; q += 256) {
+                const int64_t j = hidx[colO[q]] - c0;
+                if (j >= 0 && j < w) row[j] = 1;
+            }
+            __syncthreads();
+            int4* out = reinterpret_cast<int4*>(U + i * hp + c0);
+            for (int32_t k = threadIdx.x; k < w / 16; k += 256) out[k] = reinterpret_cast<const int4*>(row)[k];
+            __syncthreads();
+        }
+    }
+}
+
+// UT = U transposed, by 64 x 64 byte tiles through LDS (hp is a multiple of
+// 128, so the tiles cover both matrices exactly).
+__global__ void __launch_bounds__(256) k_heavy_transpose(const int32_t* __restrict__ h_dev,
+                                                          const uint8_t* __restrict__ U, uint8_t* __restrict__ UT) {
+    __shared__ uint8_t tile[64][64 + 4];
+    const int64_t hp = heavy_pad(h_dev[0]);
+    const int64_t T = hp / 64;
+    const int t = threadIdx.x;
+    const int r = t >> 2, cc = (t & 3) * 16;  // row of the tile and first of 16 columns
+    for (int64_t q = blockIdx.x; q < T * T; q += gridDim.x) {
+        const int64_t ti = q / T, tj = q % T;
+        const int4 v = *reinterpret_cast<const int4*>(U + (ti * 64 + r) * hp + tj * 64 + cc);
+        const uint32_t wv[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tile[r][cc + k] = (uint8_t)(wv[k >> 2] >> (8 * (k & 3)));
+        __syncthreads();
+        uint32_t o[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) o[k >> 2] |= (uint32_t)tile[cc + k][r] << (8 * (k & 3));
+        *reinterpret_cast<int4*>(UT + (tj * 64 + r) * hp + ti * 64 + cc) =
+            make_int4((int)o[0], (int)o[1], (int)o[2], (int)o[3]);
+        __syncthreads();
     }
 }
 
@@ -1509,10 +1542,12 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         TC_LAUNCH("heavy_place", k_heavy_place, dim3(ceil_div(hmax, 256)), dim3(256), 0, s,
                   (const int32_t*)hlist.get(), h_dev, (const int32_t*)hrank.get(), hidx.get(), horder.get());
         DevBuf<uint8_t> U((size_t)hp_max * hp_max, s), UT((size_t)hp_max * hp_max, s);
-        TC_LAUNCH("heavy_zero", k_heavy_zero, dim3(2048), dim3(256), 0, s, h_dev, U.get(), UT.get());
-        TC_LAUNCH("heavy_pack", k_heavy_pack, dim3((unsigned)hmax), dim3(256), 0, s, (const int32_t*)horder.get(),
-                  h_dev, (const int32_t*)rpO.get(), (const int32_t*)colO.get(), (const int32_t*)hidx.get(), U.get(),
-                  UT.get());
+        TC_LAUNCH("heavy_pack", k_heavy_rows, dim3((unsigned)std::min<int64_t>(hp_max, (int64_t)num_cus() * 8)),
+                  dim3(256), 0, s, (const int32_t*)horder.get(),
+                  h_dev, (const int32_t*)rpO.get(), (const int32_t*)colO.get(), (const int32_t*)hidx.get(), U.get());
+        TC_LAUNCH("heavy_transpose", k_heavy_transpose, dim3((unsigned)std::min<int64_t>(
+                                                            (hp_max / 64) * (hp_max / 64), (int64_t)num_cus() * 8)),
+                  dim3(256), 0, s, h_dev, (const uint8_t*)U.get(), UT.get());
         // one block per macro tile up to 8 per CU, a multiple of 8 (one share per XCD)
         const int64_t nm_max = hp_max / kHT;
         const int64_t tiles_max = nm_max * (nm_max + 1) / 2;
