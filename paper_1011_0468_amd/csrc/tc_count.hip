@@ -1115,32 +1115,36 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
 // heavy block
 // ---------------------------------------------------------------------------
 
-// rank of each heavy vertex in (deg, id) order, by counting smaller keys: block
+// rank of each heavy vertex in (deg, id) order, by counting smaller keys: tile
 // (bx, by) compares heavy vertices bx*256.. with the kRankChunk keys by*kRankChunk..
 // and adds its counts into rank[] (zeroed beforehand)
-constexpr int kRankChunk = 1024;
+constexpr int kRankChunk = 256;
 
 __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev,
                                                      const int32_t* __restrict__ degp, int32_t* __restrict__ rank) {
     __shared__ int32_t kd[256], kx[256];
     const int32_t h = h_dev[0];
-    const int64_t j0 = (int64_t)blockIdx.y * kRankChunk;
-    if ((int64_t)blockIdx.x * 256 >= h || j0 >= h) return;  // block-uniform
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    int32_t x = -1, dx = 0;
-    if (i < h) { x = hlist[i]; dx = degp[x]; }
-    const int64_t j1 = min((int64_t)h, j0 + kRankChunk);
-    int32_t r = 0;
-    for (int64_t jb = j0; jb < j1; jb += 256) {
-        const int64_t j = jb + threadIdx.x;
-        if (j < j1) { kx[threadIdx.x] = hlist[j]; kd[threadIdx.x] = degp[kx[threadIdx.x]]; }
-        __syncthreads();
-        const int lim = (int)min((int64_t)256, j1 - jb);
-        if (i < h)
-            for (int q = 0; q < lim; ++q) r += rank_below(kd[q], kx[q], dx, x) ? 1 : 0;
-        __syncthreads();
+    // tiles (256 heavy vertices) x (kRankChunk keys), taken with a static
+    // stride by a persistent grid sized for the device's h
+    const int64_t tx = (h + 255) / 256, ty = (h + kRankChunk - 1) / kRankChunk;
+    for (int64_t tile = blockIdx.x; tile < tx * ty; tile += gridDim.x) {  // block-uniform
+        const int64_t i = (tile % tx) * 256 + threadIdx.x;
+        const int64_t j0 = (tile / tx) * kRankChunk;
+        int32_t x = -1, dx = 0;
+        if (i < h) { x = hlist[i]; dx = degp[x]; }
+        const int64_t j1 = min((int64_t)h, j0 + kRankChunk);
+        int32_t r = 0;
+        for (int64_t jb = j0; jb < j1; jb += 256) {
+            const int64_t j = jb + threadIdx.x;
+            if (j < j1) { kx[threadIdx.x] = hlist[j]; kd[threadIdx.x] = degp[kx[threadIdx.x]]; }
+            __syncthreads();
+            const int lim = (int)min((int64_t)256, j1 - jb);
+            if (i < h)
+                for (int q = 0; q < lim; ++q) r += rank_below(kd[q], kx[q], dx, x) ? 1 : 0;
+            __syncthreads();
+        }
+        if (i < h && r) atomicAdd(&rank[i], r);
     }
-    if (i < h && r) atomicAdd(&rank[i], r);
 }
 
 __global__ void k_heavy_place(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev,
@@ -1537,7 +1541,10 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
                   (const int32_t*)heavy.get(), (const int32_t*)hpos.get(), hlist.get());
         DevBuf<int32_t> hrank(hmax, s);
         fill_i32(hrank.get(), 0, hmax, s);
-        TC_LAUNCH("heavy_rank", k_heavy_rank, dim3(ceil_div(hmax, 256), ceil_div(hmax, kRankChunk)), dim3(256), 0, s,
+        TC_LAUNCH("heavy_rank", k_heavy_rank, dim3((unsigned)std::min<int64_t>(
+                                                  (int64_t)ceil_div(hmax, 256) * (int64_t)ceil_div(hmax, kRankChunk),
+                                                  (int64_t)num_cus() * 4)),
+                  dim3(256), 0, s,
                   (const int32_t*)hlist.get(), h_dev, degp, hrank.get());
         TC_LAUNCH("heavy_place", k_heavy_place, dim3(ceil_div(hmax, 256)), dim3(256), 0, s,
                   (const int32_t*)hlist.get(), h_dev, (const int32_t*)hrank.get(), hidx.get(), horder.get());
