@@ -17,7 +17,8 @@
 // hub row is split over many waves.  rp_dot is a plain sum over entries.  In
 // rp_spmm a row that lies entirely inside one wave's range is stored
 // directly; the partial rows at range boundaries are accumulated atomically
-// into a zeroed Y (the count is additive over any split of the row).
+// into rows that rp_clear_ends zeroes first (the count is additive over any
+// split of the row).
 #include "tc_internal.h"
 #include "tc_device.h"
 
