@@ -655,10 +655,18 @@ __global__ void __launch_bounds__(576) k_finish(const int32_t* mp, const int32_t
     __shared__ int64_t red[64][9];
     const int t = threadIdx.x;
     const int q = t % 9, c = t / 9;
+    // 8 independent loads in flight per thread and round (0 is neutral for
+    // both the sums and the maximum of non-negative degrees)
     int64_t v = 0;
-    for (int32_t b = c; b < nparts; b += 64) {
-        const int64_t x = part[(int64_t)b * 9 + q];
-        v = q == 8 ? (x > v ? x : v) : v + x;
+    for (int32_t b0 = c; b0 < nparts; b0 += 64 * 8) {
+        int64_t x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int32_t b = b0 + 64 * k;
+            x[k] = b < nparts ? part[(int64_t)b * 9 + q] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v = q == 8 ? (x[k] > v ? x[k] : v) : v + x[k];
     }
     red[c][q] = v;
     __syncthreads();
