@@ -157,6 +157,25 @@ def test_rp_matches_oracle(gpu):
         assert est == oest
 
 
+@pytest.mark.parametrize("name", ["empty", "one_vertex", "isolated", "k65", "star4096", "star4097"])
+@pytest.mark.parametrize("k", [1, 3, 64])
+def test_rp_edge_cases(gpu, name, k):
+    # K_65 has 4160 CSR entries: its rows of 64 end exactly at the 4096-entry
+    # sweep-range boundary; the centre row of star4096 fills one whole range,
+    # that of star4097 spills one entry into the next
+    if name.startswith("star"):
+        N = int(name[4:])
+        G = (N + 1, np.zeros(N, np.int32), np.arange(1, N + 1, dtype=np.int32))
+    else:
+        G = GRAPHS[name]
+    _log("rp edge case %s k=%d" % (name, k))
+    g = _build(gpu, G)
+    q, est = gpu.tc_rp_trace(g, k, 11)
+    oq, oest = oracle.rp_trace(oracle.normalise(*G), k, 11)
+    assert np.array_equal(q, oq)
+    assert est == oest
+
+
 def test_rp_star_bound_and_overflow(gpu):
     # star K_{1,N}: sum over CSR entries of deg_i deg_j = 2 N^2; k * 2^33 >= 2^62
     # must be refused before any q is returned, a small k must match the oracle
