@@ -3,7 +3,7 @@
 Calls only the CPU oracle (oracle/) on inputs from the seeded generators
 (synth/); nothing here touches the device path.  Usage:
 
-    python tests/golden/make_golden.py rmat22 cl20 rmat24
+    python tests/golden/make_golden.py rmat22 cl20 rmat24 rmat24_count rmat22_top
 
 Each section writes tests/golden/<name>.json.
 """
@@ -77,6 +77,25 @@ def rmat24_count():
     g = _graph("rmat24")
     return {"workload": "R-MAT scale 24, edge factor 16, a/b/c = .57/.19/.19, generator seed 1",
             "split": [1, 1], "exact": oracle.count_split(g, 1, 1)}
+
+
+def rmat22_top():
+    # the subgraph induced by the h highest-degree vertices (degree, then id,
+    # descending) of R-MAT s22, relabelled 0..h-1 in that order; counted by the
+    # oracle (about a minute for h = 17000)
+    import numpy as np
+    n, s, d = synth.workload("rmat22")
+    deg = np.diff(_graph("rmat22")[1])
+    out = {}
+    for h in (17000,):
+        order = np.lexsort((np.arange(n), deg))[::-1][:h]
+        lab = np.full(n, -1, np.int64)
+        lab[order] = np.arange(h)
+        keep = (lab[s] >= 0) & (lab[d] >= 0)
+        sub = oracle.normalise(h, lab[s[keep]].astype(np.int32), lab[d[keep]].astype(np.int32))
+        out[str(h)] = {"m": int(len(sub[2]) // 2), "triangles": int(oracle.count(sub))}
+    return {"workload": "R-MAT scale 22 (generator seed 1), subgraph induced by the top-h degree vertices",
+            "blocks": out}
 
 
 if __name__ == "__main__":
