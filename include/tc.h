@@ -55,7 +55,9 @@ typedef struct tc_graph_s* tc_graph;
 
 /* Light/heavy threshold (section 3.2 uses deg <= m^(1/2) for light).  A vertex
    of the counted graph is heavy iff heavy_den^2 * deg^2 > heavy_num^2 * m,
-   evaluated in int64.  heavy_num = 0 makes every non-isolated vertex heavy. */
+   evaluated exactly (no overflow).  heavy_num = 0 makes every non-isolated
+   vertex heavy.  heavy_num and heavy_den above 32768 (and heavy_num < 0 or
+   heavy_den < 1) give TC_ERR_INVALID, also in tc_tuning. */
 typedef struct {
     int32_t heavy_num;   /* default 1 */
     int32_t heavy_den;   /* default 1, must be >= 1 */

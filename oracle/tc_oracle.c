@@ -219,7 +219,10 @@ int64_t or_count_bruteforce(int64_t n, const uint8_t* adj) {
 /* ------------------------------------------------------------------------- */
 
 int or_is_heavy(int64_t deg, int64_t m, int32_t a, int32_t b) {
-    return (int64_t)b * b * deg * deg > (int64_t)a * a * m;
+    /* 128-bit products: exact for every int32 a, b and int64 deg, m < 2^62 */
+    unsigned __int128 lhs = (unsigned __int128)(uint64_t)b * (uint64_t)b * (uint64_t)deg * (uint64_t)deg;
+    unsigned __int128 rhs = (unsigned __int128)(uint64_t)a * (uint64_t)a * (uint64_t)m;
+    return lhs > rhs;
 }
 
 /*

@@ -278,10 +278,19 @@ int num_cus() {
     return cus;
 }
 
+// The heavy multiplier c = heavy_num / heavy_den enters the integer test
+// heavy_den^2 deg^2 > heavy_num^2 m, which the device evaluates exactly for
+// both terms up to 2^15.
+void check_heavy_multiplier(int32_t num, int32_t den) {
+    if (den < 1 || num < 0) fail(TC_ERR_INVALID, "heavy_num must be >= 0 and heavy_den >= 1");
+    if (num > kHeavyTermMax || den > kHeavyTermMax)
+        fail(TC_ERR_INVALID, "heavy_num and heavy_den must be at most 32768");
+}
+
 CountConfig config_from(const tc_params* prm, const tc_graph_s* g, int sampled, double p) {
     CountConfig c;
     if (prm) {
-        if (prm->heavy_den < 1 || prm->heavy_num < 0) fail(TC_ERR_INVALID, "heavy_num must be >= 0 and heavy_den >= 1");
+        check_heavy_multiplier(prm->heavy_num, prm->heavy_den);
         c.heavy_num = prm->heavy_num;
         c.heavy_den = prm->heavy_den;
         if (prm->use_tuned) c = tuned_config(g, sampled, p, c);  // the table's entry replaces the split too
@@ -485,23 +494,38 @@ static void count_batch(const tc_graph_s* g, int sampled, uint64_t thr, const ui
     DevBuf<int64_t> accs((size_t)S * kCountSlots, s);
     const int K = S < 4 ? S : 4;
     std::vector<hipStream_t> side = side_streams(K);
-    hipEvent_t start = nullptr;
-    check_hip(hipEventCreateWithFlags(&start, hipEventDisableTiming), "event");
-    check_hip(hipEventRecord(start, s), "event record");
-    for (int k = 0; k < K; ++k) check_hip(hipStreamWaitEvent(side[(size_t)k], start, 0), "wait");
-    for (int32_t i = 0; i < S; ++i)
-        count_enqueue(g, sampled, thr, salts[i], cfg, side[(size_t)(i % K)], accs.get() + (size_t)i * kCountSlots);
-    std::vector<hipEvent_t> done((size_t)K);
-    for (int k = 0; k < K; ++k) {
-        check_hip(hipEventCreateWithFlags(&done[(size_t)k], hipEventDisableTiming), "event");
-        check_hip(hipEventRecord(done[(size_t)k], side[(size_t)k]), "event record");
-        check_hip(hipStreamWaitEvent(s, done[(size_t)k], 0), "wait");
-    }
+    std::vector<hipEvent_t> events;  // destroyed on every path
+    auto new_event = [&]() {
+        hipEvent_t e = nullptr;
+        check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+        events.push_back(e);
+        return e;
+    };
+    int used = 0;  // side streams that may hold work of this batch
     std::vector<int64_t> h((size_t)S * kCountSlots);
-    check_hip(hipMemcpyAsync(h.data(), accs.get(), sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, s), "acc");
-    check_hip(hipStreamSynchronize(s), "sync");
-    (void)hipEventDestroy(start);
-    for (auto e : done) (void)hipEventDestroy(e);
+    try {
+        hipEvent_t start = new_event();
+        check_hip(hipEventRecord(start, s), "event record");
+        for (int k = 0; k < K; ++k) check_hip(hipStreamWaitEvent(side[(size_t)k], start, 0), "wait");
+        used = K;
+        for (int32_t i = 0; i < S; ++i)
+            count_enqueue(g, sampled, thr, salts[i], cfg, side[(size_t)(i % K)], accs.get() + (size_t)i * kCountSlots);
+        for (int k = 0; k < K; ++k) {
+            hipEvent_t done = new_event();
+            check_hip(hipEventRecord(done, side[(size_t)k]), "event record");
+            check_hip(hipStreamWaitEvent(s, done, 0), "wait");
+        }
+        check_hip(hipMemcpyAsync(h.data(), accs.get(), sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, s), "acc");
+        check_hip(hipStreamSynchronize(s), "sync");
+    } catch (...) {
+        // kernels already queued on the side streams still use accs (and
+        // buffers returned to their streams' pools): drain them first
+        for (int k = 0; k < used; ++k) (void)hipStreamSynchronize(side[(size_t)k]);
+        (void)hipStreamSynchronize(s);
+        for (auto e : events) (void)hipEventDestroy(e);
+        throw;
+    }
+    for (auto e : events) (void)hipEventDestroy(e);
     for (int32_t i = 0; i < S; ++i) counts_from_slots(h.data() + (size_t)i * kCountSlots, &res[(size_t)i]);
 }
 
@@ -643,7 +667,7 @@ tc_status tc_rp_trace(tc_graph g, int32_t k, uint64_t seed, void* stream, int64_
 
 static CountConfig from_tuning(const tc_tuning* t) {
     CountConfig c;
-    if (t->heavy_den < 1 || t->heavy_num < 0) fail(TC_ERR_INVALID, "heavy_num must be >= 0 and heavy_den >= 1");
+    check_heavy_multiplier(t->heavy_num, t->heavy_den);
     if (t->small_dmax < 1 || t->small_dmax > 128) fail(TC_ERR_INVALID, "small_dmax must be in [1, 128]");
     if (t->vmajor_cap < 0) fail(TC_ERR_INVALID, "vmajor_cap must be >= 0");
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 16) fail(TC_ERR_INVALID, "blocks_per_cu must be in [1, 16]");

@@ -36,7 +36,7 @@ namespace {
 
 enum Acc {
     kTL = 0, kTH, kLightSources, kLightOut, kWedges, kGather, kProbes, kDmaxLarge, kBytesSmall, kBytesLarge,
-    kItemsSmall, kItemsLarge, kMp, kH, kAccN
+    kItemsSmall, kItemsLarge, kMp, kH, kHeavyOverflow, kAccN
 };
 static_assert(kAccN <= kCountSlots, "count result slots");
 
@@ -144,8 +144,22 @@ __host__ __device__ inline int64_t heavy_pad(int64_t h) { return (h + kHT - 1) /
 // classification and light work
 // ---------------------------------------------------------------------------
 
+// b^2 deg^2 > a^2 m without overflow: the entry points cap a and b at 2^15 and
+// m < 2^30 (2m fits int32), so a^2 m < 2^60; x = b deg < 2^46, and x >= 2^31
+// already gives x^2 >= 2^62 > a^2 m.
 __device__ __forceinline__ bool is_heavy(int64_t deg, int64_t m, int32_t a, int32_t b) {
-    return (int64_t)b * b * deg * deg > (int64_t)a * a * m;
+    const uint64_t x = (uint64_t)(uint32_t)b * (uint64_t)deg;
+    const uint64_t y = (uint64_t)(uint32_t)a * (uint64_t)(uint32_t)a * (uint64_t)m;
+    if (x >> 31) return true;
+    return x * x > y;
+}
+
+// The device's heavy count, clamped to the host bound every heavy buffer is
+// sized for (it always holds: h < 2 m'^(1/2) / c; k_heavy_list flags a
+// violation, which the read-back turns into TC_ERR_OVERFLOW).
+__device__ __forceinline__ int32_t heavy_count(const int32_t* h_dev, int32_t hmax) {
+    const int32_t h = h_dev[0];
+    return h < hmax ? h : hmax;
 }
 
 // Orders one wave's shared-table writes before its later reads.  LDS
@@ -639,9 +653,10 @@ __global__ void k_items(int64_t n, const int32_t* __restrict__ cnt, const int32_
 }
 
 __global__ void k_heavy_list(int64_t n, const int32_t* __restrict__ heavy, const int32_t* __restrict__ hpos,
-                             int32_t* __restrict__ hlist) {
+                             int32_t hmax, int32_t* __restrict__ hlist, int64_t* __restrict__ acc) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && hpos[n] > hmax) acc[kHeavyOverflow] = 1;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
-        if (heavy[x]) hlist[hpos[x]] = (int32_t)x;
+        if (heavy[x] && hpos[x] < hmax) hlist[hpos[x]] = (int32_t)x;
 }
 
 // zero the first heavy_pad(h)^2 bytes of U and UT (h from device)
@@ -1129,9 +1144,10 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
 constexpr int kRankChunk = 256;
 
 __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev,
-                                                     const int32_t* __restrict__ degp, int32_t* __restrict__ rank) {
+                                                     int32_t hmax, const int32_t* __restrict__ degp,
+                                                     int32_t* __restrict__ rank) {
     __shared__ int32_t kd[256], kx[256];
-    const int32_t h = h_dev[0];
+    const int32_t h = heavy_count(h_dev, hmax);
     // tiles (256 heavy vertices) x (kRankChunk keys), taken with a static
     // stride by a persistent grid sized for the device's h
     const int64_t tx = (h + 255) / 256, ty = (h + kRankChunk - 1) / kRankChunk;
@@ -1155,10 +1171,10 @@ __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ 
     }
 }
 
-__global__ void k_heavy_place(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev,
+__global__ void k_heavy_place(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev, int32_t hmax,
                               const int32_t* __restrict__ rank, int32_t* __restrict__ hidx,
                               int32_t* __restrict__ horder) {
-    const int32_t h = h_dev[0];
+    const int32_t h = heavy_count(h_dev, hmax);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < h; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t x = hlist[i];
         hidx[x] = rank[i];
@@ -1174,11 +1190,11 @@ __global__ void k_heavy_place(const int32_t* __restrict__ hlist, const int32_t* 
 // needs no separate clearing.
 constexpr int kRowChunk = 16384;
 __global__ void __launch_bounds__(256) k_heavy_rows(const int32_t* __restrict__ horder,
-                                                     const int32_t* __restrict__ h_dev,
+                                                     const int32_t* __restrict__ h_dev, int32_t hmax,
                                                      const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
                                                      const int32_t* __restrict__ hidx, uint8_t* __restrict__ U) {
     __shared__ __attribute__((aligned(16))) uint8_t row[kRowChunk];
-    const int32_t h = h_dev[0];
+    const int32_t h = heavy_count(h_dev, hmax);
     const int64_t hp = heavy_pad(h);
     for (int64_t i = blockIdx.x; i < hp; i += gridDim.x) {
         const int32_t b = i < h ? rpO[horder[i]] : 0;
@@ -1201,10 +1217,10 @@ __global__ void __launch_bounds__(256) k_heavy_rows(const int32_t* __restrict__ 
 
 // UT = U transposed, by 64 x 64 byte tiles through LDS (hp is a multiple of
 // 128, so the tiles cover both matrices exactly).
-__global__ void __launch_bounds__(256) k_heavy_transpose(const int32_t* __restrict__ h_dev,
+__global__ void __launch_bounds__(256) k_heavy_transpose(const int32_t* __restrict__ h_dev, int32_t hmax,
                                                           const uint8_t* __restrict__ U, uint8_t* __restrict__ UT) {
     __shared__ uint8_t tile[64][64 + 4];
-    const int64_t hp = heavy_pad(h_dev[0]);
+    const int64_t hp = heavy_pad(heavy_count(h_dev, hmax));
     const int64_t T = hp / 64;
     const int t = threadIdx.x;
     const int r = t >> 2, cc = (t & 3) * 16;  // row of the tile and first of 16 columns
@@ -1246,10 +1262,11 @@ constexpr int kHRow = kHK + 16;  // LDS row stride: 16-lane groups of 16-byte re
 // XCDs in contiguous ranges, so blocks of one XCD share the U^T panels of
 // their columns in that XCD's L2.
 __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ U, const uint8_t* __restrict__ UT,
-                                                     const int32_t* __restrict__ h_dev, int64_t* __restrict__ acc) {
+                                                     const int32_t* __restrict__ h_dev, int32_t hmax,
+                                                     int64_t* __restrict__ acc) {
     __shared__ __attribute__((aligned(16))) uint8_t As[kHT * kHRow];
     __shared__ __attribute__((aligned(16))) uint8_t Bs[kHT * kHRow];
-    const int32_t h = h_dev[0];
+    const int32_t h = heavy_count(h_dev, hmax);
     if (h < 3) return;  // block-uniform
     const int64_t hp = heavy_pad(h);
     const int64_t nm = hp / kHT;
@@ -1545,36 +1562,39 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     if (hmax >= 3) {
         DevBuf<int32_t> hlist(hmax, s), hidx(n, s), horder(hmax, s);
         const int32_t* h_dev = hpos.get() + n;
+        const int32_t hm = (int32_t)hmax;
         TC_LAUNCH("heavy_list", k_heavy_list, dim3(grid_for(n, 256)), dim3(256), 0, s, n,
-                  (const int32_t*)heavy.get(), (const int32_t*)hpos.get(), hlist.get());
+                  (const int32_t*)heavy.get(), (const int32_t*)hpos.get(), hm, hlist.get(), acc);
         DevBuf<int32_t> hrank(hmax, s);
         fill_i32(hrank.get(), 0, hmax, s);
         TC_LAUNCH("heavy_rank", k_heavy_rank, dim3((unsigned)std::min<int64_t>(
                                                   (int64_t)ceil_div(hmax, 256) * (int64_t)ceil_div(hmax, kRankChunk),
                                                   (int64_t)num_cus() * 4)),
                   dim3(256), 0, s,
-                  (const int32_t*)hlist.get(), h_dev, degp, hrank.get());
+                  (const int32_t*)hlist.get(), h_dev, hm, degp, hrank.get());
         TC_LAUNCH("heavy_place", k_heavy_place, dim3(ceil_div(hmax, 256)), dim3(256), 0, s,
-                  (const int32_t*)hlist.get(), h_dev, (const int32_t*)hrank.get(), hidx.get(), horder.get());
+                  (const int32_t*)hlist.get(), h_dev, hm, (const int32_t*)hrank.get(), hidx.get(), horder.get());
         DevBuf<uint8_t> U((size_t)hp_max * hp_max, s), UT((size_t)hp_max * hp_max, s);
         TC_LAUNCH("heavy_pack", k_heavy_rows, dim3((unsigned)std::min<int64_t>(hp_max, (int64_t)num_cus() * 8)),
                   dim3(256), 0, s, (const int32_t*)horder.get(),
-                  h_dev, (const int32_t*)rpO.get(), (const int32_t*)colO.get(), (const int32_t*)hidx.get(), U.get());
+                  h_dev, hm, (const int32_t*)rpO.get(), (const int32_t*)colO.get(), (const int32_t*)hidx.get(), U.get());
         TC_LAUNCH("heavy_transpose", k_heavy_transpose, dim3((unsigned)std::min<int64_t>(
                                                             (hp_max / 64) * (hp_max / 64), (int64_t)num_cus() * 8)),
-                  dim3(256), 0, s, h_dev, (const uint8_t*)U.get(), UT.get());
+                  dim3(256), 0, s, h_dev, hm, (const uint8_t*)U.get(), UT.get());
         // one block per macro tile up to 8 per CU, a multiple of 8 (one share per XCD)
         const int64_t nm_max = hp_max / kHT;
         const int64_t tiles_max = nm_max * (nm_max + 1) / 2;
         const int64_t mblocks = std::min<int64_t>((int64_t)num_cus() * 8, (tiles_max + 7) / 8 * 8);
         TC_LAUNCH("heavy_mfma", k_heavy_mfma, dim3((unsigned)mblocks), dim3(256), 0, s, (const uint8_t*)U.get(),
-                  (const uint8_t*)UT.get(), h_dev, acc);
+                  (const uint8_t*)UT.get(), h_dev, hm, acc);
     }
     TC_LAUNCH("finish", k_finish, dim3(1), dim3(576), 0, s, mp_dev, (const int32_t*)hpos.get() + n,
               (const int64_t*)cpart.get(), (int32_t)cgrid, acc);
 }
 
 void counts_from_slots(const int64_t* hacc, tc_counts* out) {
+    if (hacc[kHeavyOverflow])
+        fail(TC_ERR_OVERFLOW, "heavy vertex count exceeds its bound (the heavy threshold test overflowed)");
     tc_counts res{};
     res.light = hacc[kTL];
     res.heavy = hacc[kTH];

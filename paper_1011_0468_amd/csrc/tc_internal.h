@@ -210,6 +210,9 @@ void rp_trace(const tc_graph_s* g, int32_t k, uint64_t seed, hipStream_t s, int6
 // ---------------------------------------------------------------------------
 
 bool p_valid(double p);
+// largest heavy_num / heavy_den accepted (the heavy test is exact up to it)
+constexpr int32_t kHeavyTermMax = 1 << 15;
+void check_heavy_multiplier(int32_t num, int32_t den);
 CountConfig config_from(const tc_params* prm, const tc_graph_s* g, int sampled, double p);
 double rescale(int64_t T, double p);
 int32_t max_degree(const tc_graph_s* g, hipStream_t s);

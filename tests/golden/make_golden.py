@@ -3,7 +3,7 @@
 Calls only the CPU oracle (oracle/) on inputs from the seeded generators
 (synth/); nothing here touches the device path.  Usage:
 
-    python tests/golden/make_golden.py rmat22 cl20 rmat24 rmat24_count rmat22_top
+    python tests/golden/make_golden.py rmat22 rmat22_splits cl20 rmat24 rmat24_count rmat22_top serve20
 
 Each section writes tests/golden/<name>.json.
 """
@@ -64,13 +64,51 @@ def _rp_job(args):
 
 
 def rmat24():
-    ls = [0, 1, 63, 64, 127, 200, 255]
-    with mp.Pool(4) as pool:
-        qs = pool.map(_rp_job, [("rmat24", l, 0) for l in ls])
+    # every one of the k = 256 vectors, one by one; the graph is normalised in
+    # the parent so that the forked workers share it
+    k = 256
     g = _graph("rmat24")
+    with mp.Pool(8) as pool:
+        qs = pool.map(_rp_job, [("rmat24", l, 0) for l in range(k)], chunksize=4)
     return {"workload": "R-MAT scale 24, edge factor 16, a/b/c = .57/.19/.19, generator seed 1",
-            "k": 256, "seed": 0, "sampled_q": {str(l): int(q) for l, q in zip(ls, qs)},
-            "m": int(len(g[2]) // 2)}
+            "k": k, "seed": 0, "q": [int(q) for q in qs], "m": int(len(g[2]) // 2)}
+
+
+def _split_job(args):
+    name, p, seed, a, b = args
+    g = _graph(name)
+    t = time.time()
+    gp = g if p == 1.0 else oracle.sample(g, p, seed)
+    r = oracle.count_split(gp, a, b)
+    r.update(p=p, seed=seed, split=[a, b], oracle_seconds=round(time.time() - t, 2))
+    return r
+
+
+def rmat22_splits():
+    # the light/heavy split of every operating point of the benchmark (p = 1,
+    # 0.5, 0.1, 0.05, seed 0) for every heavy multiplier c = a/b the autotuner
+    # may pick (1/4, 1/2, 2; c = 1 is in rmat22.json)
+    _graph("rmat22")
+    jobs = [("rmat22", p, 0, a, b) for p in (1.0, 0.5, 0.1, 0.05) for a, b in ((1, 4), (1, 2), (2, 1))]
+    with mp.Pool(6) as pool:
+        res = pool.map(_split_job, jobs, chunksize=1)
+    return {"workload": "R-MAT scale 22, edge factor 16, a/b/c = .57/.19/.19, generator seed 1",
+            "counts": res}
+
+
+def serve20():
+    # the scale-20 end of the serving mix (request 0's generator seed) at the
+    # three keep probabilities of the mix, sample seeds 0, 1, 2
+    n, s, d = synth.serving_graph(0, 20)
+    g = oracle.normalise(n, s, d)
+    out = []
+    for seed, p in enumerate((1.0, 0.5, 0.1)):
+        gp = g if p == 1.0 else oracle.sample(g, p, seed)
+        r = oracle.count_split(gp, 1, 1)
+        r.update(p=p, seed=seed)
+        out.append(r)
+    return {"workload": "R-MAT scale 20, edge factor 16, a/b/c = .57/.19/.19, generator seed 1000 (serving request 0)",
+            "n": n, "pairs": int(len(s)), "counts": out}
 
 
 def rmat24_count():

@@ -75,3 +75,18 @@ def test_profile_hooks_without_device():
     assert L.tc_profile_read(b"light_small", ctypes.byref(ms), ctypes.byref(cnt)) == 0
     assert ms.value == 0.0 and cnt.value == 0
     assert L.tc_profile_read(None, None, None) == _native.TC_ERR_INVALID
+
+
+def test_heavy_multiplier_terms_are_capped():
+    # heavy_num and heavy_den above 2^15 are refused before any device work:
+    # the handle below is never dereferenced, because argument validation
+    # precedes every use of it
+    L = _native.load()
+    dummy = ctypes.c_void_p(16)
+    c = _native.TcCounts()
+    for num, den in ((1 << 15, 1 << 16), (1 << 20, 1), (1, (1 << 15) + 1), (-1, 1), (1, 0)):
+        prm = _native.TcParams(num, den, 0)
+        assert L.tc_count_exact(dummy, ctypes.byref(prm), None, ctypes.byref(c)) == _native.TC_ERR_INVALID
+        t = _native.TcTuning(num, den, 128, 1024, 8)
+        assert L.tc_tune_set(dummy, ctypes.c_double(0.5), ctypes.byref(t)) == _native.TC_ERR_INVALID
+    assert b"32768" in L.tc_last_error() or b">= 1" in L.tc_last_error()

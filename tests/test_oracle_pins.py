@@ -216,6 +216,19 @@ def test_is_heavy_tie_is_light():
     assert oracle.is_heavy(6, 100, 1, 2)
 
 
+def test_is_heavy_exact_where_64_bit_products_wrap():
+    # the test deg > c m^(1/2), c = a/b, as b^2 deg^2 > a^2 m in exact
+    # integers (section 3.2): checked against Python's unbounded integers on
+    # operands whose 64-bit products would wrap
+    cases = [(1, 1 << 24, 1 << 20, 1),             # a^2 m = 2^64: light
+             ((1 << 31) - 1, 1 << 29, 1, 1 << 15),  # b^2 deg^2 ~ 2^92: heavy
+             (1 << 30, (1 << 30) - 1, 1 << 15, 1 << 15),
+             (46341, (1 << 31) - 1, 1, 1), (46340, (1 << 31) - 1, 1, 1),
+             (3037000500, 1 << 62, 1, 2), ((1 << 31) - 1, (1 << 30) - 1, (1 << 31) - 1, 1)]
+    for deg, m, a, b in cases:
+        assert oracle.is_heavy(deg, m, a, b) == (b * b * deg * deg > a * a * m), (deg, m, a, b)
+
+
 # --------------------------------------------------------------- sample ----
 
 def test_sample_p1_keeps_all_and_symmetry():
