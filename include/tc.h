@@ -135,6 +135,24 @@ tc_status tc_estimate(tc_graph g, double p, const uint64_t* seeds, int32_t num_s
                       int32_t num_groups, const tc_params* prm, void* stream,
                       tc_counts* per_seed, double* per_seed_est, double* mom_est);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the
+   single-seed form of tc_estimate, bit-identical to tc_estimate(g, p, &seed,
+   1, 1, prm, stream, out, est, NULL), whose every intermediate buffer lives
+   in one fixed device array of 64 MiB that the library reserves per GPU (held
+   until the process ends).  The call makes no hipMalloc, hipFree or other
+   allocating call; it enqueues on `stream` and synchronises it before
+   returning.  The graph g (built earlier, e.g. by tc_build_csr) and the host
+   outputs are the caller's.  A count that needs more scratch than the array
+   holds (roughly graphs beyond a few hundred thousand edges) is refused with
+   TC_ERR_BUDGET before any device work.  Calls on one GPU share its array:
+   the library serialises them (one at a time per device), and the array keeps
+   the last call's contents; each call clears what it needs.  Profiling hooks
+   record nothing during this call.  est may be NULL.  Other errors as
+   tc_estimate. */
+tc_status tc_estimate_noalloc(tc_graph g, double p, uint64_t seed, const tc_params* prm, void* stream,
+                              tc_counts* out, double* est);
+
 /* One stage of tc_estimate_adaptive. */
 typedef struct {
     double p;          /* keep probability of the stage */

@@ -135,6 +135,17 @@ def tc_estimate(g, p, seeds, num_groups=1, heavy=(1, 1), tuned=False, stream=Non
     return [c.as_dict() for c in per], list(ests), mom.value
 
 
+def tc_estimate_noalloc(g, p, seed, heavy=(1, 1), tuned=False, stream=None):
+    """Single-seed estimate whose buffers all live in the library's fixed
+    device scratch array (no device allocation): (counts dict, estimate)."""
+    c = TcCounts()
+    est = ctypes.c_double(0.0)
+    prm = _params(heavy, tuned)
+    check(_native.load().tc_estimate_noalloc(g.handle, float(p), int(seed) & (2 ** 64 - 1), ctypes.byref(prm),
+                                             _stream_ptr(stream), ctypes.byref(c), ctypes.byref(est)))
+    return c.as_dict(), est.value
+
+
 def tc_estimate_adaptive(g, p0, tol, seed0=0, num_seeds=8, num_groups=4, max_stages=32, heavy=(1, 1),
                          tuned=False, stream=None):
     """Stages of the adaptive keep probability (list of dicts p, estimate,

@@ -94,7 +94,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 
 # every symbol declared in include/tc.h
 EXPORTS = ["tc_set_allocator", "tc_build_csr", "tc_graph_info", "tc_graph_csr", "tc_graph_read", "tc_sample",
-           "tc_count_exact", "tc_estimate", "tc_estimate_adaptive", "tc_triple_estimate", "tc_rp_trace", "tc_tune_set", "tc_tune_get", "tc_autotune",
+           "tc_count_exact", "tc_estimate", "tc_estimate_noalloc", "tc_estimate_adaptive", "tc_triple_estimate", "tc_rp_trace", "tc_tune_set", "tc_tune_get", "tc_autotune",
            "tc_graph_free", "tc_last_error",
            "tc_request_bytes", "tc_server_create", "tc_server_clock", "tc_server_submit", "tc_server_poll",
            "tc_server_stats", "tc_server_destroy",
@@ -122,6 +122,7 @@ def load():
         "tc_sample": [vp, dbl, u64, vp, P(vp)],
         "tc_count_exact": [vp, P(TcParams), vp, P(TcCounts)],
         "tc_estimate": [vp, dbl, P(u64), i32, i32, P(TcParams), vp, P(TcCounts), P(dbl), P(dbl)],
+        "tc_estimate_noalloc": [vp, dbl, u64, P(TcParams), vp, P(TcCounts), P(dbl)],
         "tc_estimate_adaptive": [vp, dbl, dbl, u64, i32, i32, i32, P(TcParams), vp, P(TcStage), P(i32), P(dbl)],
         "tc_triple_estimate": [vp, dbl, u64, i32, i64, u64, vp, P(TcTripleResult)],
         "tc_rp_trace": [vp, i32, u64, vp, P(i64), P(dbl)],

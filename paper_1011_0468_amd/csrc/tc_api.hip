@@ -122,6 +122,8 @@ AllocRegion* set_thread_region(AllocRegion* r) {
 void* dev_alloc(size_t bytes, hipStream_t s) {
     if (t_region) {
         if (void* p = t_region->try_alloc(bytes ? bytes : 1)) return p;
+        if (t_region->strict)
+            fail(TC_ERR_BUDGET, "allocation of " + std::to_string(bytes) + " bytes does not fit the fixed region");
         t_region->spilled += (int64_t)bytes;
     }
     tc_alloc_fn a;
@@ -188,7 +190,13 @@ hipEvent_t take_event() {
 
 }  // namespace
 
+static thread_local bool t_no_profile = false;
+
+NoProfileScope::NoProfileScope() : prev(t_no_profile) { t_no_profile = true; }
+NoProfileScope::~NoProfileScope() { t_no_profile = prev; }
+
 LaunchScope::LaunchScope(const char* n, hipStream_t s) : name(n), stream(s) {
+    if (t_no_profile) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on || !selected(n)) return;
     hipEvent_t e = take_event();

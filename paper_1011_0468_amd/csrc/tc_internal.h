@@ -35,6 +35,7 @@ void set_last_error(const std::string& msg);
 // spilled); try_free returns false for pointers it does not own.
 struct AllocRegion {
     int64_t spilled = 0;
+    bool strict = false;  // a failed try_alloc is an error instead of a spill
     virtual void* try_alloc(size_t bytes) = 0;
     virtual bool try_free(void* p) = 0;
     virtual ~AllocRegion() = default;
@@ -82,6 +83,13 @@ struct DevBuf {
 // ---------------------------------------------------------------------------
 // Profiling of launches (events on the launch stream)
 // ---------------------------------------------------------------------------
+
+// While alive on a thread, launches of that thread record no profiling events.
+struct NoProfileScope {
+    bool prev;
+    NoProfileScope();
+    ~NoProfileScope();
+};
 
 struct LaunchScope {
     const char* name;
