@@ -64,26 +64,50 @@ def _traffic(kernel, workload, tunings):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(workload, ps, seed, gpu_counts):
-    """The oracle (single-threaded C) on a bounded sample of the same workload."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload, ps, seeds, gpu_ms=None):
+    """The oracle (single-threaded C, this thread pinned to one core) on a
+    bounded sample of the same workload: sampling plus exact split count of
+    each sampled graph, for the operating points ps and the sample seeds.
+    gpu_ms (p -> ms of one call) gives the device's rate on the same legs."""
     import oracle
     import synth
     g = oracle.normalise(*synth.workload(workload))
-    edges, secs = 0, 0.0
-    parity = True
-    for p in ps:
-        t = time.perf_counter()
-        gp = oracle.sample(g, p, seed)
-        r = oracle.count_split(gp, 1, 1)
-        secs += time.perf_counter() - t
-        edges += r["m"]
-        if p in gpu_counts and gpu_counts[p] != r["triangles"]:
-            parity = False
-    return {"value": edges / secs, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "%s, p in %s, seed %d: oracle sample + exact split count of each sampled graph "
-                      "(%.1f s single-threaded; the p=1 and p=0.5 legs are left out for time)"
-                      % (workload, list(ps), seed, secs),
-            "parity_with_gpu": parity}
+    allowed = sorted(os.sched_getaffinity(0))
+    pin = allowed[0]
+    os.sched_setaffinity(0, {pin})
+    try:
+        edges, secs, counts = 0, 0.0, {}
+        for p in ps:
+            for sd in seeds:
+                t = time.perf_counter()
+                gp = oracle.sample(g, p, sd)
+                r = oracle.count_split(gp, 1, 1)
+                secs += time.perf_counter() - t
+                edges += r["m"]
+                counts[(p, sd)] = r
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    out = {"value": edges / secs, "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "sample": "%s, p in %s, seeds %s: oracle sample + exact split count of each sampled graph "
+                     "(%.1f s on one pinned core; the p=1 and p=0.5 legs take minutes and are left out)"
+                     % (workload, list(ps), list(seeds), secs),
+           "pinned_cpu": pin, "nproc": len(allowed), "cpu_model": _cpu_model()}
+    if gpu_ms:
+        # the device on the same legs (seed 0 calls, per-call wall time)
+        e0 = sum(counts[(p, seeds[0])]["m"] for p in ps)
+        t0 = sum(gpu_ms[p] for p in ps) / 1e3
+        out["gpu_same_legs_edges_per_s"] = e0 / t0
+    return out, counts
 
 
 def batched(args):
@@ -201,20 +225,20 @@ def triples(args):
                                  "seed": args.seed}}), flush=True)
 
 
-def serve(args):
-    """Serving: ``--requests`` R-MAT requests (scale uniform in [10, 20], edge
-    factor 16, generator seed 1000 + i) counted at p uniform in {1, .5, .1}
-    (sample seed i) by the serving engine with an 8 GiB arena.  Poisson
-    arrivals (seed 12345) at 0.5, 0.8 and 0.95 x the measured one-at-a-time
-    capacity; 4 lanes against 1 lane (one request at a time, arrival order) on
-    the same trace.  Latency = result ready - arrival; every request's counts
-    must be identical in every run."""
+def serving_trace(N, loads=(0.5, 0.8, 0.95), pinned=True, log=True):
+    """Serving: N R-MAT requests (scale uniform in [10, 20], edge factor 16,
+    generator seed 1000 + i) counted at p uniform in {1, .5, .1} (sample seed
+    i) by the serving engine with an 8 GiB arena.  The one-at-a-time capacity
+    is measured closed-loop; then Poisson arrivals (seed 12345) at each load
+    factor x that capacity are served by 4 lanes and by 1 lane (one request at
+    a time, arrival order: one launch sequence per request) on the same trace.
+    Latency = result ready - arrival; every request's counts must be identical
+    in every run.  Returns the summary dict."""
     import concurrent.futures as cf
     import numpy as np
     import synth
     import paper_1011_0468_amd as tc
 
-    N = args.requests
     scales, ps = synth.serving_requests(N)
     reqs = [None] * N
     t = time.perf_counter()
@@ -222,17 +246,16 @@ def serve(args):
         futs = {ex.submit(synth.serving_graph, i, scales[i]): i for i in range(N)}
         for k, f in enumerate(cf.as_completed(futs)):
             reqs[futs[f]] = f.result()
-            if (k + 1) % 200 == 0:
+            if log and (k + 1) % 200 == 0:
                 print("generated %d/%d requests (%.1f s)" % (k + 1, N, time.perf_counter() - t),
                       file=sys.stderr, flush=True)
     pairs = int(sum(len(r[1]) for r in reqs))
     budget = 8 << 30
-    pinned = not args.pageable
+    keep = []
     if pinned:
         # request payloads in page-locked host memory, as a serving front end
         # would keep them: the copies to the device then run at DMA speed
         import torch
-        keep = []
         for i, (n, s, d) in enumerate(reqs):
             ps_ = torch.empty(len(s), dtype=torch.int32, pin_memory=True)
             pd_ = torch.empty(len(d), dtype=torch.int32, pin_memory=True)
@@ -258,30 +281,41 @@ def serve(args):
         out = {"lanes": lanes, "p50_ms": round(float(np.percentile(lat, 50)), 3),
                "p99_ms": round(float(np.percentile(lat, 99)), 3), "req_per_s": round(N / span, 2),
                "edges_per_s": edges / span, "span_s": round(span, 3), "arena_peak": st["arena_peak"]}
-        print("lanes %d: %s" % (lanes, json.dumps(out)), file=sys.stderr, flush=True)
+        if log:
+            print("lanes %d: %s" % (lanes, json.dumps(out)), file=sys.stderr, flush=True)
         return out, [x["counts"] for x in res]
 
     closed1, ref = run(1, None)
     closed4, c4 = run(4, None)
     assert c4 == ref
     mu1 = closed1["req_per_s"]
-    loads = {}
-    for f in (0.5, 0.8, 0.95):
+    out_loads = {}
+    for f in loads:
         arr = synth.poisson_arrivals(N, f * mu1, 12345)
         r4, c = run(4, arr)
         assert c == ref
         r1, c = run(1, arr)
         assert c == ref
-        loads[str(f)] = {"lambda_req_per_s": round(f * mu1, 2), "lanes4": r4, "fifo": r1}
-    head = loads["0.8"]
+        out_loads[str(f)] = {"lambda_req_per_s": round(f * mu1, 2), "lanes4": r4, "fifo": r1}
+    return {"requests": N, "pairs": pairs, "capacity_req_per_s": {"fifo": mu1, "lanes4": closed4["req_per_s"]},
+            "closed_loop": {"fifo": closed1, "lanes4": closed4}, "loads": out_loads,
+            "identical_alone_and_in_mix": True, "host_payloads": "pinned" if pinned else "pageable",
+            "budget_bytes": budget, "arrival_seed": 12345}
+
+
+def serve(args):
+    """--workload serve: the full 1000-request trace at 0.5, 0.8, 0.95 x capacity."""
+    import synth
+    r = serving_trace(args.requests, pinned=not args.pageable)
+    head = r["loads"]["0.8"]
     print(json.dumps({"metric": "serving p99 latency at 0.8 x one-at-a-time capacity", "value": head["lanes4"]["p99_ms"],
                       "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "int32", "data": "synthetic",
-                      "fifo_p99_ms": head["fifo"]["p99_ms"], "capacity_req_per_s": {"fifo": mu1,
-                                                                                  "lanes4": closed4["req_per_s"]},
-                      "closed_loop": {"fifo": closed1, "lanes4": closed4}, "loads": loads,
-                      "identical_alone_and_in_mix": True, "host_payloads": "pinned" if pinned else "pageable",
-                      "config": {"workload": "serve", "requests": N, "pairs": pairs, "scales": [10, 20],
-                                 "ps": list(synth.SERVE_P), "budget_bytes": budget, "arrival_seed": 12345}}),
+                      "fifo_p99_ms": head["fifo"]["p99_ms"], "capacity_req_per_s": r["capacity_req_per_s"],
+                      "closed_loop": r["closed_loop"], "loads": r["loads"],
+                      "identical_alone_and_in_mix": True, "host_payloads": r["host_payloads"],
+                      "config": {"workload": "serve", "requests": r["requests"], "pairs": r["pairs"],
+                                 "scales": [10, 20], "ps": list(synth.SERVE_P), "budget_bytes": r["budget_bytes"],
+                                 "arrival_seed": 12345}}),
           flush=True)
 
 
@@ -374,6 +408,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0)
     ap.add_argument("--requests", type=int, default=1000, help="serving workload: number of requests")
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="default workload: requests of the short serving trace whose p50/p99 the line reports "
+                         "(0: none)")
     ap.add_argument("--pageable", action="store_true",
                     help="serving workload: keep request payloads in pageable host memory")
     ap.add_argument("--tunings", default=None,
@@ -492,11 +529,16 @@ def main():
     ms_tot, launches, model = kern[dom]
     achieved = (model / (ms_tot / 1e3)) / 1e9 if ms_tot > 0 else 0.0
     traffic = _traffic(dom, args.workload, tunings)
+    wedge_bytes = 4 * sum(c["wedges"] for c in res)
+    all_light_model = sum(c["model_bytes_small"] + c["model_bytes_large"] for c in res)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "avg_launch_ms": round(ms_tot / max(launches, 1), 4), "launches": launches,
-                "model_bytes_per_launch": int(model / max(launches, 1))}
+                "model_bytes_per_launch": int(model / max(launches, 1)),
+                "model": "list bytes of the light closure (per work item the anchor's list and row offsets, "
+                         "per iterated entry 8 B, per probe 4 B)"}
 
+    phases, phase_ms = phase_breakdown(tc, step, res, info, csr_ms, pairs=len(s))
     line = {
         "metric": "sampled-graph edges/sec (1 MI355X) at R-MAT s22",
         "value": value,
@@ -515,15 +557,119 @@ def main():
                              if tuned else "light iff deg <= sqrt(m')"),
                    "csr": "int32, resident in HBM"},
         "roofline": roofline,
+        "light_wedge_model": {"bytes_per_step": wedge_bytes, "list_bytes_per_step": all_light_model,
+                              "note": "the method's lower bound: one 4-byte probe per light wedge"},
+        "phases": phases,
         "csr_build_ms": round(csr_ms, 2),
         "per_call_ms": dict(zip([str(p) for p in ps], per_call_ms)),
         "tunings": tunings,
         "results": [{k: c[k] for k in ("p", "m", "triangles", "light", "heavy", "n_heavy", "est")} for c in res],
     }
+    line["parity"] = golden_parity(args.workload, args.seed, res, tunings if tuned else None)
+    if args.serve_requests > 0:
+        sv = serving_trace(args.serve_requests, loads=(0.8,), log=False)
+        head = sv["loads"]["0.8"]
+        line["serving"] = {"requests": sv["requests"], "load": "0.8 x one-at-a-time capacity",
+                           "p50_ms": head["lanes4"]["p50_ms"], "p99_ms": head["lanes4"]["p99_ms"],
+                           "fifo_p50_ms": head["fifo"]["p50_ms"], "fifo_p99_ms": head["fifo"]["p99_ms"],
+                           "req_per_s": head["lanes4"]["req_per_s"], "edges_per_s": head["lanes4"]["edges_per_s"],
+                           "capacity_req_per_s": sv["capacity_req_per_s"],
+                           "identical_alone_and_in_mix": True,
+                           "trace": "R-MAT scale uniform in [10, 20], p in {1, .5, .1}, Poisson arrivals seed 12345"}
     if not args.no_cpu_baseline:
+        low = [p for p in ps if p <= 0.1]
+        gms = {p: per_call_ms[ps.index(p)] for p in low}
+        cb, counts = cpu_baseline(args.workload, low, [args.seed, args.seed + 1, args.seed + 2], gms)
         gc = {c["p"]: c["triangles"] for c in res}
-        line["cpu_baseline"] = cpu_baseline(args.workload, [p for p in ps if p <= 0.1], args.seed, gc)
+        cb["parity_with_gpu"] = all(counts[(p, args.seed)]["triangles"] == gc[p] for p in low)
+        line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
+
+
+def _mfma_ops(h):
+    """int8 MFMA operations the heavy kernel executes for h heavy vertices:
+    2 * 128^3 * (J - I + 1) per 128 x 128 macro tile I <= J."""
+    nm = (h + 127) // 128
+    return 2 * 128 ** 3 * sum((J + 1) * (J + 2) // 2 for J in range(nm)) if h >= 3 else 0
+
+
+def phase_breakdown(tc, step, res, info, csr_ms, pairs):
+    """One extra step with every launch bracketed by HIP events (outside the
+    timed region): kernel time per step of the path, next to the bytes or
+    operations its model says it must move (SURVEY-style declared models:
+    sample 4*2m + 4(n+1) read + 4*2m' + 8(n+1) written; orientation and split
+    4*2m' + 4(n+1) read + 4m' + 4(n+1) + 4n written; light closure: the list
+    model; heavy block: executed int8 MFMA operations; CSR build 8 B per input
+    pair read, 4*2m + 8n + 4 written)."""
+    import torch
+    tc.profile.select([])
+    tc.profile.reset()
+    tc.profile.enable(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) * 1e3
+    tc.profile.enable(False)
+    ms = {ph: tc.profile.read("@" + ph)[0] for ph in ("sample", "orient", "light", "heavy", "finish")}
+    n, m = info["n"], info["m"]
+    sampled = [c for c in res if c["p"] < 1.0]
+    b_sample = sum(4 * 2 * m + 4 * (n + 1) + 4 * 2 * c["m"] + 8 * (n + 1) for c in sampled)
+    b_orient = sum(4 * 2 * c["m"] + 4 * (n + 1) + 4 * c["m"] + 4 * (n + 1) + 4 * n for c in res)
+    b_light = sum(c["model_bytes_small"] + c["model_bytes_large"] for c in res)
+    ops_heavy = sum(_mfma_ops(c["n_heavy"]) for c in res)
+    b_csr = 8 * pairs + 4 * 2 * m + 8 * n + 4
+
+    def hbm(b, t_ms):
+        gbs = b / (t_ms / 1e3) / 1e9 if t_ms > 0 else 0.0
+        return {"ms": round(t_ms, 4), "model_bytes": int(b), "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    out = {"sample": hbm(b_sample, ms["sample"]), "orient_split": hbm(b_orient, ms["orient"]),
+           "light": hbm(b_light, ms["light"]),
+           "heavy": {"ms": round(ms["heavy"], 4), "mfma_ops": ops_heavy,
+                     "tops": round(ops_heavy / (ms["heavy"] / 1e3) / 1e12, 2) if ms["heavy"] > 0 else 0.0,
+                     "frac_int8_peak": round(ops_heavy / (ms["heavy"] / 1e3) / 1e12 / 5000.0, 5)
+                     if ms["heavy"] > 0 else 0.0},
+           "finish_ms": round(ms["finish"], 4),
+           "kernel_ms_sum": round(sum(ms.values()), 4), "step_wall_ms": round(wall, 4),
+           "csr_build": hbm(b_csr, csr_ms)}
+    out["light"]["wedge_bound_bytes"] = 4 * sum(c["wedges"] for c in res)
+    out["light"]["frac_wedge_bound"] = round(out["light"]["wedge_bound_bytes"] / (ms["light"] / 1e3) / 1e9
+                                             / HBM_PEAK_GBS, 4) if ms["light"] > 0 else 0.0
+    out["note"] = ("kernel time from HIP events around every launch of one untimed step; the csr_build time is "
+                   "the wall time of tc_build_csr")
+    return out, ms
+
+
+def golden_parity(workload, seed, res, tunings):
+    """The step's counts against the oracle's stored values (tests/golden,
+    written by tests/golden/make_golden.py from the oracle alone): per point
+    the triangle count, and the light/heavy split for the multiplier used."""
+    if workload != "rmat22" or seed != 0:
+        return None
+    gd = os.path.join(ROOT, "tests", "golden")
+    want = {}
+    try:
+        for c in json.load(open(os.path.join(gd, "rmat22.json")))["counts"]:
+            want[(c["p"], 1, 1)] = c
+        if os.path.exists(os.path.join(gd, "rmat22_splits.json")):
+            for c in json.load(open(os.path.join(gd, "rmat22_splits.json")))["counts"]:
+                want[(c["p"], c["split"][0], c["split"][1])] = c
+    except (OSError, ValueError, KeyError):
+        return None
+    out = {}
+    for c in res:
+        t = tunings[str(c["p"])] if tunings else {"heavy_num": 1, "heavy_den": 1}
+        a, b = t["heavy_num"], t["heavy_den"]
+        import math
+        gcd = math.gcd(a, b) or 1
+        w = want.get((c["p"], a // gcd, b // gcd))
+        if w is None:
+            out[str(c["p"])] = "no stored split for c = %d/%d" % (a, b)
+            continue
+        ok = all(c[k] == w[k] for k in ("triangles", "light", "heavy", "n_heavy", "m"))
+        out[str(c["p"])] = "equal" if ok else "DIFFERENT"
+    return out
 
 
 if __name__ == "__main__":

@@ -160,6 +160,7 @@ namespace {
 
 struct Pending {
     const char* name;
+    const char* phase;
     hipEvent_t a, b;
 };
 
@@ -191,11 +192,15 @@ hipEvent_t take_event() {
 }  // namespace
 
 static thread_local bool t_no_profile = false;
+static thread_local const char* t_phase = nullptr;
+
+PhaseScope::PhaseScope(const char* ph) : prev(t_phase) { t_phase = ph; }
+PhaseScope::~PhaseScope() { t_phase = prev; }
 
 NoProfileScope::NoProfileScope() : prev(t_no_profile) { t_no_profile = true; }
 NoProfileScope::~NoProfileScope() { t_no_profile = prev; }
 
-LaunchScope::LaunchScope(const char* n, hipStream_t s) : name(n), stream(s) {
+LaunchScope::LaunchScope(const char* n, hipStream_t s) : name(n), phase(t_phase), stream(s) {
     if (t_no_profile) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on || !selected(n)) return;
@@ -214,7 +219,7 @@ LaunchScope::~LaunchScope() {
         return;
     }
     if (hipEventRecord(e1, stream) != hipSuccess) return;
-    g_pending.push_back({name, (hipEvent_t)ev0, e1});
+    g_pending.push_back({name, phase, (hipEvent_t)ev0, e1});
 }
 
 void profile_collect() {
@@ -230,6 +235,11 @@ void profile_collect() {
             auto& slot = g_prof[p.name];
             slot.first += ms;
             slot.second += 1;
+            if (p.phase) {
+                auto& ph = g_prof[std::string("@") + p.phase];
+                ph.first += ms;
+                ph.second += 1;
+            }
         }
         g_event_pool.push_back(p.a);
         g_event_pool.push_back(p.b);
@@ -440,6 +450,7 @@ tc_status tc_sample(tc_graph g, double p, uint64_t seed, void* stream, tc_graph*
             o->home = s;
             o->row_ptr = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(n + 1), s);
             o->deg = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s);
+            PhaseScope ph("sample");
             DevBuf<uint64_t> bits(NW, s);
             DevBuf<int32_t> wpre(NW + 1, s);
             fill_i32(wpre.get(), 0, 1, s);

@@ -1413,6 +1413,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     DevBuf<uint64_t> keep;
     DevBuf<int32_t> kpre, rps, degs, cols, srcs;
     if (sampled) {
+        PhaseScope ph("sample");
         keep.reset(NW, s);
         kpre.reset(NW + 1, s);
         rps.reset(n + 1, s);
@@ -1431,6 +1432,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     }
 
     // 2. orientation by (deg, id): compacted up lists N+(x), in CSR order
+    PhaseScope ph_orient("orient");
     DevBuf<uint64_t> ubits(NW, s);
     DevBuf<int32_t> upre(NW + 1, s);
     DevBuf<uint8_t> cls(n, s);
@@ -1453,6 +1455,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
               (const int32_t*)dplus.get(), mp_dev, cfg.heavy_num, cfg.heavy_den, heavy.get(), code.get(),
               dminus.get());
     scan_exclusive_i32(dminus.get(), rpD.get(), n, s);  // slots of each vertex's v-major descriptors
+    PhaseScope ph_light("light");
     DevBuf<int4> rowQ(n, s);
     DevBuf<int64_t> Wu(n, s), cw(n, s);
     DevBuf<int2> packD(vcap > 0 ? g->m : 1, s);  // v-major descriptors, rpD[v].. for vertex v
@@ -1560,6 +1563,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
 
     // 5. heavy phase: sized by the bound, trimmed to the device's h inside the kernels
     if (hmax >= 3) {
+        PhaseScope ph("heavy");
         DevBuf<int32_t> hlist(hmax, s), hidx(n, s), horder(hmax, s);
         const int32_t* h_dev = hpos.get() + n;
         const int32_t hm = (int32_t)hmax;
@@ -1588,6 +1592,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         TC_LAUNCH("heavy_mfma", k_heavy_mfma, dim3((unsigned)mblocks), dim3(256), 0, s, (const uint8_t*)U.get(),
                   (const uint8_t*)UT.get(), h_dev, hm, acc);
     }
+    PhaseScope ph_finish("finish");
     TC_LAUNCH("finish", k_finish, dim3(1), dim3(576), 0, s, mp_dev, (const int32_t*)hpos.get() + n,
               (const int64_t*)cpart.get(), (int32_t)cgrid, acc);
 }

@@ -249,6 +249,7 @@ int64_t build_csr_bytes(int64_t n, int64_t num_pairs) {
 }
 
 int build_csr(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst, hipStream_t s, tc_graph_s* g) {
+    PhaseScope ph("csr");
     const int nb = key_bits_half(n);
     if (2 * nb <= 32) return build_csr_t<uint32_t>(n, num_pairs, src, dst, nb, s, g);
     return build_csr_t<uint64_t>(n, num_pairs, src, dst, nb, s, g);

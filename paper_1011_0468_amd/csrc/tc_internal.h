@@ -91,8 +91,17 @@ struct NoProfileScope {
     ~NoProfileScope();
 };
 
+// While alive on a thread, profiled launches of that thread are also
+// accumulated under "@<phase>" (the step of the path they belong to).
+struct PhaseScope {
+    const char* prev;
+    explicit PhaseScope(const char* phase);
+    ~PhaseScope();
+};
+
 struct LaunchScope {
     const char* name;
+    const char* phase;
     hipStream_t stream;
     void* ev0 = nullptr;
     LaunchScope(const char* n, hipStream_t s);

@@ -217,6 +217,7 @@ __global__ void __launch_bounds__(256) k_rp_bound(const int32_t* __restrict__ sr
 }  // namespace
 
 void rp_trace(const tc_graph_s* g, int32_t k, uint64_t seed, hipStream_t s, int64_t* q_host) {
+    PhaseScope ph("rp");
     const int64_t n = g->n, E2 = 2 * g->m;
     for (int32_t l = 0; l < k; ++l) q_host[l] = 0;
     if (n == 0 || E2 == 0) return;

@@ -132,17 +132,29 @@ def test_failed_request_does_not_disturb_the_mix(gpu):
 
 
 def test_serving_workload_largest_request(gpu):
-    # the scale-20 end of the serving mix under the default 8 GiB budget
+    # the scale-20 end of the serving mix under the default 8 GiB budget, at
+    # the mix's three keep probabilities: every request against the oracle's
+    # counts stored in tests/golden/serve20.json and against the stand-alone call
+    import json
+    import os
     tc = gpu
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "serve20.json")))
+    want = {c["seed"]: c for c in gold["counts"]}
     n, s, d = synth.serving_graph(0, 20)
+    assert n == gold["n"] and len(s) == gold["pairs"]
     with tc.Server(8 << 30, lanes=4) as sv:
-        for k, p in enumerate((1.0, 0.5, 0.1)):
-            sv.submit(k, p, k, n=n, src=s, dst=d)
+        for k, c in want.items():
+            sv.submit(k, c["p"], k, n=n, src=s, dst=d)
         res = sv.drain()
     g = tc.tc_build_csr(n, s, d)
+    assert len(res) == len(want)
     for x in res:
-        p = (1.0, 0.5, 0.1)[x["id"]]
+        w = want[x["id"]]
+        p = w["p"]
         assert x["status"] == 0 and x["spilled_bytes"] == 0 and x["peak_bytes"] <= x["reserved_bytes"]
+        for k in ("triangles", "light", "heavy", "n_heavy", "m"):
+            assert x["counts"][k] == w[k], (p, k, x["counts"][k], w[k])
+        assert x["estimate"] == oracle.estimate(w["triangles"], p)
         per, _, _ = tc.tc_estimate(g, p, [x["id"]])
         assert x["counts"] == per[0]
         _log("scale 20 p=%g: T=%d latency %.1f ms, peak %.0f MiB of %.0f MiB reserved"
