@@ -386,6 +386,50 @@ def heavy_stress(args):
           flush=True)
 
 
+def rp_workload(args):
+    """Random-projection trace on R-MAT scale 24 (k = 256 Rademacher vectors,
+    seed 0): time per call, the sweeps' model bytes (CSR read twice per
+    64-vector sweep plus the Y rows written and gathered) and the relative
+    error of the estimate against the exact count (measured once, untimed)."""
+    import torch
+    import synth
+    import paper_1011_0468_amd as tc
+    n, s, d = synth.workload("rmat24")
+    g = tc.tc_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    del s, d
+    info = g.info()
+    k = 256
+    for _ in range(args.warmup):
+        tc.tc_rp_trace(g, k, args.seed)
+    tc.profile.select([])
+    tc.profile.reset()
+    tc.profile.enable(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        q, est = tc.tc_rp_trace(g, k, args.seed)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    tc.profile.enable(False)
+    kern = {}
+    for name in ("rp_spmm", "rp_dot", "rp_bound", "rp_clear"):
+        tot, cnt = tc.profile.read(name)
+        if cnt:
+            kern[name] = {"ms_per_call": round(tot / args.steps, 4), "launches_per_call": cnt // args.steps}
+    T = tc.tc_count_exact(g)["triangles"]
+    E2 = 2 * info["m"]
+    sweeps = (k + 63) // 64
+    model = sweeps * (2 * 8 * E2 + 2 * 4 * 64 * info["n"]) + info["n"] * k // 8
+    gbs = model / (ms / 1e3) / 1e9
+    print(json.dumps({"metric": "random-projection trace time (1 MI355X) at R-MAT s24, k=256", "value": round(ms, 3),
+                      "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+                      "dtype": "int64", "data": "synthetic", "estimate": est, "exact": T, "rel_error": est / T - 1.0,
+                      "kernels": kern, "model_bytes": model, "roofline": {"bound": "hbm", "achieved": round(gbs, 1),
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                      "config": {"workload": "rmat24", "n": info["n"], "m": info["m"], "k": k, "seed": args.seed}}),
+          flush=True)
+
+
 def copy_probe(mib):
     """A plain device copy of known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -445,6 +489,9 @@ def main():
         return
     if args.workload == "heavy":
         heavy_stress(args)
+        return
+    if args.workload == "rp":
+        rp_workload(args)
         return
 
     import synth

@@ -484,68 +484,62 @@ tc_status tc_count_exact(tc_graph g, const tc_params* prm, void* stream, tc_coun
     });
 }
 
-// Side streams for batched work (default priority, created once per device).
-static std::vector<hipStream_t> side_streams(int want) {
-    static std::mutex mu;
-    static std::map<int, std::vector<hipStream_t>> per_dev;
-    int dev = 0;
-    check_hip(hipGetDevice(&dev), "get device");
-    std::lock_guard<std::mutex> lk(mu);
-    auto& v = per_dev[dev];
-    while ((int)v.size() < want) {
-        hipStream_t st = nullptr;
-        check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "stream create");
-        v.push_back(st);
-    }
-    return std::vector<hipStream_t>(v.begin(), v.begin() + want);
-}
-
-// Counts of several independent sparsified copies of g, enqueued without host
-// synchronisation round-robin on side streams that start after the caller's
-// stream and join it again; one read-back for the whole batch.
+// Counts of several independent sparsified copies of g.  The copies of a
+// chunk of seeds are sampled into one union graph (copy k of the chunk is
+// component k) and counted together: every kernel launch of the chunk covers
+// all of its seeds, and each component's counts equal a count of that copy
+// alone.  Chunks are sized so that the union stays within int32 ids and a
+// memory budget.  Without sampling (p = 1) every seed counts g itself.
 static void count_batch(const tc_graph_s* g, int sampled, uint64_t thr, const uint64_t* salts, int32_t S,
                         const CountConfig& cfg, hipStream_t s, std::vector<tc_counts>& res) {
     res.resize((size_t)S);
-    if (S == 1) {
+    if (S == 1 || !sampled) {
         count_core(g, sampled, thr, salts[0], cfg, s, &res[0]);
+        for (int32_t i = 1; i < S; ++i) res[(size_t)i] = res[0];
         return;
     }
-    DevBuf<int64_t> accs((size_t)S * kCountSlots, s);
-    const int K = S < 4 ? S : 4;
-    std::vector<hipStream_t> side = side_streams(K);
-    std::vector<hipEvent_t> events;  // destroyed on every path
-    auto new_event = [&]() {
-        hipEvent_t e = nullptr;
-        check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
-        events.push_back(e);
-        return e;
-    };
-    int used = 0;  // side streams that may hold work of this batch
-    std::vector<int64_t> h((size_t)S * kCountSlots);
-    try {
-        hipEvent_t start = new_event();
-        check_hip(hipEventRecord(start, s), "event record");
-        for (int k = 0; k < K; ++k) check_hip(hipStreamWaitEvent(side[(size_t)k], start, 0), "wait");
-        used = K;
-        for (int32_t i = 0; i < S; ++i)
-            count_enqueue(g, sampled, thr, salts[i], cfg, side[(size_t)(i % K)], accs.get() + (size_t)i * kCountSlots);
-        for (int k = 0; k < K; ++k) {
-            hipEvent_t done = new_event();
-            check_hip(hipEventRecord(done, side[(size_t)k]), "event record");
-            check_hip(hipStreamWaitEvent(s, done, 0), "wait");
+    const int64_t npad = (g->n + kUnionAlign - 1) / kUnionAlign * kUnionAlign;
+    const double p = (double)thr / 9007199254740992.0;
+    const double kept = p * (double)(2 * g->m) * 1.1 + 4096.0;  // expected entries per copy, with slack
+    const double per_copy = 110.0 * (double)npad + 48.0 * kept;  // bytes the union count takes per copy
+    int64_t kc = S;
+    kc = std::min<int64_t>(kc, (int64_t)((double)(1 << 30) / kept));
+    kc = std::min<int64_t>(kc, npad > 0 ? ((int64_t)1 << 31) / (npad + 1) - 1 : kc);
+    kc = std::min<int64_t>(kc, (int64_t)(48.0 * (double)(1ull << 30) / per_copy));
+    if (kc < 1) kc = 1;
+    for (int32_t i0 = 0; i0 < S; i0 += (int32_t)kc) {
+        const int32_t K = (int32_t)std::min<int64_t>(kc, S - i0);
+        if (K == 1) {
+            count_core(g, sampled, thr, salts[i0], cfg, s, &res[(size_t)i0]);
+            continue;
         }
-        check_hip(hipMemcpyAsync(h.data(), accs.get(), sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, s), "acc");
-        check_hip(hipStreamSynchronize(s), "sync");
-    } catch (...) {
-        // kernels already queued on the side streams still use accs (and
-        // buffers returned to their streams' pools): drain them first
-        for (int k = 0; k < used; ++k) (void)hipStreamSynchronize(side[(size_t)k]);
-        (void)hipStreamSynchronize(s);
-        for (auto e : events) (void)hipEventDestroy(e);
-        throw;
+        DevBuf<uint64_t> sd(K, s);
+        check_hip(hipMemcpyAsync(sd.get(), salts + i0, sizeof(uint64_t) * (size_t)K, hipMemcpyHostToDevice, s),
+                  "salts");
+        DevBuf<int32_t> comp((size_t)K * (size_t)npad, s), off((size_t)K + 1, s);
+        DevBuf<int64_t> mk(K, s), accs((size_t)K * kCountSlots, s);
+        tc_graph_s* gu = new tc_graph_s();
+        std::vector<int64_t> h((size_t)K * kCountSlots);
+        try {
+            sample_union_replicas(g, K, sd.get(), thr, s, gu, comp.get(), off.get(), mk.get());
+            CountUnion un;
+            un.K = K;
+            un.comp = comp.get();
+            un.off = off.get();
+            un.mk = mk.get();
+            count_union(gu, un, cfg, s, accs.get());
+            check_hip(hipMemcpyAsync(h.data(), accs.get(), sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, s),
+                      "acc");
+            check_hip(hipStreamSynchronize(s), "sync");
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            graph_release(gu);
+            throw;
+        }
+        graph_release(gu);
+        for (int32_t k = 0; k < K; ++k)
+            counts_from_slots(h.data() + (size_t)k * kCountSlots, &res[(size_t)(i0 + k)]);
     }
-    for (auto e : events) (void)hipEventDestroy(e);
-    for (int32_t i = 0; i < S; ++i) counts_from_slots(h.data() + (size_t)i * kCountSlots, &res[(size_t)i]);
 }
 
 // Median of the group means of the counts (groups of consecutive seeds; for

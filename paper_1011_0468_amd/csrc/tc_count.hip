@@ -93,10 +93,14 @@ __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__
     const int lane = __lane_id();
     const int64_t NW = (E2 + 63) / 64;
     const int64_t valid = E2_dev ? (int64_t)E2_dev[0] : E2;
+    const int64_t NWv = (valid + 63) / 64;  // words holding valid entries
     const int64_t last = valid > 0 ? valid - 1 : 0;
     const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t w0 = wave * 4; w0 < NW; w0 += nwaves * 4) {
+    // words past the valid entries only need a zero count (the scan runs over
+    // all NW words; their bits are never read)
+    for (int64_t w = NWv + (wave * 64 + lane); w < NW; w += nwaves * 64) ucnt[w] = 0;
+    for (int64_t w0 = wave * 4; w0 < NWv; w0 += nwaves * 4) {
         int32_t u[4], v[4];
         bool in[4];
 #pragma unroll
@@ -123,7 +127,7 @@ __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__
             }
             const bool up = in[k] && below;
             const uint64_t bu = ballot64(up);
-            if (lane == k && w0 + k < NW) {
+            if (lane == k && w0 + k < NWv) {
                 ubits[w0 + k] = bu;
                 ucnt[w0 + k] = __popcll(bu);
             }
@@ -189,13 +193,15 @@ __device__ __forceinline__ bool vmajor(int32_t len, int32_t dv, int32_t vcap) {
 
 // per vertex: heavy flag, code = d+(x) if x is a light source (light, d+ >= 2)
 // else 0, and d-(x) = deg - d+ (the in-degree of the orientation)
+// (in a union of components, m' is that of x's component: mk[comp[x]])
 __global__ void k_vertex_prep(int64_t n, const int32_t* __restrict__ degp, const int32_t* __restrict__ dplus,
-                              const int32_t* __restrict__ mp_dev, int32_t ha, int32_t hb, int32_t* __restrict__ heavy,
+                              const int32_t* __restrict__ mp_dev, const int32_t* __restrict__ comp,
+                              const int64_t* __restrict__ mk, int32_t ha, int32_t hb, int32_t* __restrict__ heavy,
                               int32_t* __restrict__ code, int32_t* __restrict__ dminus) {
-    const int64_t mp = mp_dev[0];
+    const int64_t mp = comp ? 0 : mp_dev[0];
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t dg = degp[x];
-        const bool hv = dg > 0 && is_heavy(dg, mp, ha, hb);
+        const bool hv = dg > 0 && is_heavy(dg, comp ? mk[comp[x]] : mp, ha, hb);
         heavy[x] = hv ? 1 : 0;
         const int32_t dp = dplus[x];
         code[x] = !hv && dp >= 2 ? dp : 0;
@@ -356,7 +362,7 @@ __device__ __forceinline__ void work_groups(uint64_t mask, const int4& q, int64_
                                             const int4* __restrict__ rowQ, int32_t* __restrict__ colO, int32_t vcap,
                                             int2* __restrict__ packU, int2* __restrict__ packD,
                                             unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
-                                            int64_t& gsum) {
+                                            int64_t* __restrict__ Gx, int64_t& gsum) {
     constexpr int P = 64 / G;
     const int grp = lane / G;
     const int pos = lane & (G - 1);
@@ -384,20 +390,26 @@ __device__ __forceinline__ void work_groups(uint64_t mask, const int4& q, int64_
         bitonic_lanes<G>(key, idx, lane);
         // rowQ of the vertex that lands on this lane, from the lane that loaded it
         const int4 qv = make_int4(__shfl(qw.x, idx, 64), __shfl(qw.y, idx, 64), 0, __shfl(qw.w, idx, 64));
-        int64_t wu = 0;
+        int64_t wu = 0, gl = 0;
         if (in) {
             const int32_t v = (int32_t)(uint32_t)key;
             colO[rs + pos] = v;
-            int2 pk = pair_desc(rs, d, pos, qv, true, vcap, wu, gsum);
+            int2 pk = pair_desc(rs, d, pos, qv, true, vcap, wu, gl);
             if (pk.y < 0) {
                 packD[claim_vmajor(cw, v, -pk.y)] = make_int2(pk.x, -pk.y);
                 pk = make_int2(0, 0);
             }
             packU[rs + pos] = pk;
         }
+        gsum += gl;
 #pragma unroll
         for (int J = G / 2; J >= 1; J >>= 1) wu += __shfl_xor(wu, J, 64);
         if (pos == 0 && mine >= 0) Wu[x0 + mine] = wu;
+        if (Gx) {  // per-list gather statistic (unions of components)
+#pragma unroll
+            for (int J = G / 2; J >= 1; J >>= 1) gl += __shfl_xor(gl, J, 64);
+            if (pos == 0 && mine >= 0) Gx[x0 + mine] = gl;
+        }
     }
 }
 
@@ -477,15 +489,15 @@ __device__ __forceinline__ void work_wide_lists(uint64_t mask, const int4& q, in
                                                 const int4* __restrict__ rowQ, int32_t* __restrict__ colO,
                                                 int32_t vcap, int2* __restrict__ packU, int2* __restrict__ packD,
                                                 unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
-                                                int64_t& gsum) {
+                                                int64_t* __restrict__ Gx, int64_t& gsum) {
     while (mask) {
         const int l = __builtin_ctzll(mask);
         mask &= mask - 1;
         const int32_t rs = __builtin_amdgcn_readlane(q.x, l);
         const int32_t d = __builtin_amdgcn_readlane(q.y, l);
-        int64_t wu = 0;
+        int64_t wu = 0, gl = 0;
         if (d <= 64 * R) {
-            work_wide_list<R>(rs, d, lane, rowQ, colO, vcap, packU, packD, cw, wu, gsum);
+            work_wide_list<R>(rs, d, lane, rowQ, colO, vcap, packU, packD, cw, wu, gl);
         } else {
             for (int32_t k0 = 0; k0 < d; k0 += 256) {
                 uint64_t vk[4];
@@ -494,11 +506,16 @@ __device__ __forceinline__ void work_wide_lists(uint64_t mask, const int4& q, in
                     const int32_t k = k0 + 64 * b + lane;
                     vk[b] = k < d ? (uint32_t)colO[rs + k] : 0;
                 }
-                strip_work<4>(vk, k0, rs, d, false, lane, rowQ, colO, vcap, packU, packD, cw, wu, gsum);
+                strip_work<4>(vk, k0, rs, d, false, lane, rowQ, colO, vcap, packU, packD, cw, wu, gl);
             }
         }
+        gsum += gl;
         wu = wave_sum(wu);
         if (lane == 0) Wu[x0 + l] = wu;
+        if (Gx) {  // per-list gather statistic (unions of components)
+            gl = wave_sum(gl);
+            if (lane == 0) Gx[x0 + l] = gl;
+        }
     }
 }
 
@@ -522,7 +539,8 @@ __global__ void __launch_bounds__(256) k_work_lanes(int64_t n, const int4* __res
                                                      int32_t* __restrict__ colO, int32_t vcap,
                                                      int2* __restrict__ packU, int2* __restrict__ packD,
                                                      unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
-                                                     int32_t* __restrict__ wide, int64_t* __restrict__ acc) {
+                                                     int64_t* __restrict__ Gx, int32_t* __restrict__ wide,
+                                                     int64_t* __restrict__ acc) {
     const int lane = __lane_id();
     const int64_t gw = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * 4;
@@ -532,17 +550,17 @@ __global__ void __launch_bounds__(256) k_work_lanes(int64_t n, const int4* __res
         const int4 q = x < n ? rowQ[x] : make_int4(0, 0, 0, 0);
         const int32_t d = q.y;
         if (x < n && !(d >= 2 && d <= 128)) Wu[x] = 0;
-        work_groups<4>(ballot64(d >= 2 && d <= 4), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
-        work_groups<8>(ballot64(d > 4 && d <= 8), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
-        work_groups<16>(ballot64(d > 8 && d <= 16), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
-        work_groups<32>(ballot64(d > 16 && d <= 32), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
-        work_groups<64>(ballot64(d > 32 && d <= 64), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
-        work_wide_lists<2>(ballot64(d > 64 && d <= 128), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
+        work_groups<4>(ballot64(d >= 2 && d <= 4), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, Gx, gsum);
+        work_groups<8>(ballot64(d > 4 && d <= 8), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, Gx, gsum);
+        work_groups<16>(ballot64(d > 8 && d <= 16), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, Gx, gsum);
+        work_groups<32>(ballot64(d > 16 && d <= 32), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, Gx, gsum);
+        work_groups<64>(ballot64(d > 32 && d <= 64), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, Gx, gsum);
+        work_wide_lists<2>(ballot64(d > 64 && d <= 128), q, x0, lane, rowQ, colO, vcap, packU, packD, cw, Wu, Gx, gsum);
         append_rows(ballot64(d > 128 && d <= 256), x0, lane, wide + 1);
         append_rows(ballot64(d > 256 && d <= 512), x0, lane, wide + (n + 1) + 1);
         append_rows(ballot64(d > 512), x0, lane, wide + 2 * (n + 1) + 1);
     }
-    add_gather(gsum, acc);
+    if (!Gx) add_gather(gsum, acc);
 }
 
 // Anchor work of the light sources with 32 R < d+ <= 64 R (R = 16: every
@@ -554,7 +572,7 @@ __global__ void __launch_bounds__(256) k_work_wide(const int32_t* __restrict__ L
                                                     int32_t* __restrict__ colO, int32_t vcap,
                                                     int2* __restrict__ packU, int2* __restrict__ packD,
                                                     unsigned long long* __restrict__ cw, int64_t* __restrict__ Wu,
-                                                    int64_t* __restrict__ acc) {
+                                                    int64_t* __restrict__ Gx, int64_t* __restrict__ acc) {
     static_assert(kSortCap == 64 * 16, "list classes of k_work_wide");
     const int lane = __lane_id();
     const int32_t cnt = L[-1];
@@ -563,9 +581,9 @@ __global__ void __launch_bounds__(256) k_work_wide(const int32_t* __restrict__ L
          i += gridDim.x * 4) {
         const int32_t x = L[i];
         const int4 q = rowQ[x];  // wave-uniform
-        work_wide_lists<R>(1ull, q, x, lane, rowQ, colO, vcap, packU, packD, cw, Wu, gsum);
+        work_wide_lists<R>(1ull, q, x, lane, rowQ, colO, vcap, packU, packD, cw, Wu, Gx, gsum);
     }
-    add_gather(gsum, acc);
+    if (!Gx) add_gather(gsum, acc);
 }
 
 __device__ __forceinline__ int32_t items_of(int64_t w, int32_t len) {
@@ -581,6 +599,39 @@ __device__ __forceinline__ int32_t cw_end(unsigned long long c) { return (int32_
 //   per item: anchor row offsets (8 B) + staging N+(anchor) (4 B per entry);
 //   per iterated descriptor (d+ of them for u-major, the v-major count): 8 B;
 //   per probe: the streamed entry (4 B).
+// Per-vertex part of the classification: the item counts of x's bin, and
+// x's contribution to the statistics st (sources, out, wedges, probes,
+// bytes_s, bytes_l, items_s, items_l) and to the largest block-bin d+.
+__device__ __forceinline__ void classify_vertex(int64_t x, const int32_t* __restrict__ code,
+                                                const int32_t* __restrict__ dplus, const int64_t* __restrict__ Wu,
+                                                const unsigned long long* __restrict__ cw,
+                                                const int32_t* __restrict__ rpD, int32_t small_dmax,
+                                                int32_t* __restrict__ nsm, int32_t* __restrict__ nlg,
+                                                int32_t* __restrict__ nhg, int64_t (&st)[8], int64_t& dmax) {
+    const int32_t c = code[x];
+    const int32_t dp = dplus[x];
+    if (c > 0) { st[0] += 1; st[1] += c; st[2] += (int64_t)c * (c - 1) / 2; }
+    const unsigned long long c2 = cw[x];
+    const int64_t wu = Wu[x], wv = cw_len(c2);
+    const int32_t nv = cw_end(c2) - rpD[x];
+    const int32_t cu = items_of(wu, dp);
+    const int32_t cv = items_of(wv, nv);
+    const int64_t bytes = (int64_t)(cu + cv) * (8 + 4 * (int64_t)dp) + (wu > 0 ? 8 * (int64_t)dp : 0) +
+                          8 * (int64_t)(cv > 0 ? nv : 0) + 4 * (wu + wv);
+    st[3] += wu + wv;
+    const bool small = dp <= small_dmax;
+    const bool huge = dp > kLdsDcap;
+    nsm[x] = small ? cu + cv : 0;
+    nlg[x] = (!small && !huge) ? cu + cv : 0;
+    nhg[x] = huge ? cu + cv : 0;
+    if (small) { st[4] += bytes; st[6] += cu + cv; }
+    else {
+        st[5] += bytes;
+        st[7] += cu + cv;
+        if (cu + cv > 0) dmax = dp > dmax ? dp : dmax;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __restrict__ code,
                                                    const int32_t* __restrict__ dplus, const int64_t* __restrict__ Wu,
                                                    const unsigned long long* __restrict__ cw,
@@ -590,30 +641,8 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
                                                    int64_t* __restrict__ part) {
     int64_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sources, out, wedges, probes, bytes_s, bytes_l, items_s, items_l
     int64_t dmax = 0;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = code[x];
-        const int32_t dp = dplus[x];
-        if (c > 0) { st[0] += 1; st[1] += c; st[2] += (int64_t)c * (c - 1) / 2; }
-        const unsigned long long c2 = cw[x];
-        const int64_t wu = Wu[x], wv = cw_len(c2);
-        const int32_t nv = cw_end(c2) - rpD[x];
-        const int32_t cu = items_of(wu, dp);
-        const int32_t cv = items_of(wv, nv);
-        const int64_t bytes = (int64_t)(cu + cv) * (8 + 4 * (int64_t)dp) + (wu > 0 ? 8 * (int64_t)dp : 0) +
-                              8 * (int64_t)(cv > 0 ? nv : 0) + 4 * (wu + wv);
-        st[3] += wu + wv;
-        const bool small = dp <= small_dmax;
-        const bool huge = dp > kLdsDcap;
-        nsm[x] = small ? cu + cv : 0;
-        nlg[x] = (!small && !huge) ? cu + cv : 0;
-        nhg[x] = huge ? cu + cv : 0;
-        if (small) { st[4] += bytes; st[6] += cu + cv; }
-        else {
-            st[5] += bytes;
-            st[7] += cu + cv;
-            if (cu + cv > 0) dmax = dp > dmax ? dp : dmax;
-        }
-    }
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        classify_vertex(x, code, dplus, Wu, cw, rpD, small_dmax, nsm, nlg, nhg, st, dmax);
     __shared__ int64_t red[4][9];
     const int wv_ = threadIdx.x >> 6;
 #pragma unroll
@@ -633,6 +662,74 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
         }
         part[(int64_t)blockIdx.x * 9 + threadIdx.x] = v;
     }
+}
+
+// The classification of a union of components: every block takes a
+// contiguous range of whole 256-vertex windows (one component each, the
+// component starts being multiples of kUnionAlign), and adds its statistics,
+// the per-list gather statistic Gx of the light sources included, into the
+// result slots of each component it covers.
+__device__ __forceinline__ void flush_comp_stats(int32_t c, int64_t (&st)[8], int64_t& gth, int64_t& dmax,
+                                                 int64_t* __restrict__ acc) {
+    __shared__ int64_t red[4][10];
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) st[q] = wave_sum(st[q]);
+    gth = wave_sum(gth);
+    dmax = wave_max(dmax);
+    if (__lane_id() == 0) {
+        for (int q = 0; q < 8; ++q) red[w][q] = st[q];
+        red[w][8] = gth;
+        red[w][9] = dmax;
+    }
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        const int q = threadIdx.x;
+        int64_t v = red[0][q];
+        for (int i = 1; i < 4; ++i) v = q == 9 ? (red[i][q] > v ? red[i][q] : v) : v + red[i][q];
+        const int slot[10] = {kLightSources, kLightOut, kWedges, kProbes, kBytesSmall, kBytesLarge, kItemsSmall,
+                              kItemsLarge, kGather, kDmaxLarge};
+        int64_t* a = acc + (int64_t)c * kCountSlots + slot[q];
+        if (q == 9) atomicMax((unsigned long long*)a, (unsigned long long)v);
+        else if (v) atomicAdd((unsigned long long*)a, (unsigned long long)v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) st[q] = 0;
+    gth = 0;
+    dmax = 0;
+}
+
+__global__ void __launch_bounds__(256) k_classify_union(int64_t n, const int32_t* __restrict__ comp,
+                                                         const int32_t* __restrict__ code,
+                                                         const int32_t* __restrict__ dplus,
+                                                         const int64_t* __restrict__ Wu,
+                                                         const int64_t* __restrict__ Gx,
+                                                         const unsigned long long* __restrict__ cw,
+                                                         const int32_t* __restrict__ rpD, int32_t small_dmax,
+                                                         int32_t* __restrict__ nsm, int32_t* __restrict__ nlg,
+                                                         int32_t* __restrict__ nhg, int64_t* __restrict__ acc) {
+    const int64_t windows = (n + 255) / 256;
+    const int64_t per = (windows + gridDim.x - 1) / gridDim.x;
+    const int64_t w0 = (int64_t)blockIdx.x * per;
+    const int64_t w1 = min(windows, w0 + per);
+    int64_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t gth = 0, dmax = 0;
+    int32_t cur = -1;
+    for (int64_t wi = w0; wi < w1; ++wi) {
+        const int64_t xs = wi * 256;
+        const int32_t c = comp[xs];  // block-uniform: one component per window
+        if (c != cur) {
+            if (cur >= 0) flush_comp_stats(cur, st, gth, dmax, acc);
+            cur = c;
+        }
+        const int64_t x = xs + threadIdx.x;
+        if (x < n) {
+            classify_vertex(x, code, dplus, Wu, cw, rpD, small_dmax, nsm, nlg, nhg, st, dmax);
+            if (code[x] > 0) gth += Gx[x];
+        }
+    }
+    if (cur >= 0) flush_comp_stats(cur, st, gth, dmax, acc);
 }
 
 // items of anchor x: (x, r) for the u-major ranges r of N+(x), then (~x, r)
@@ -695,6 +792,16 @@ __global__ void __launch_bounds__(576) k_finish(const int32_t* mp, const int32_t
     if (t == 0) {
         acc[kMp] = mp[0];
         acc[kH] = hp[0];
+    }
+}
+
+// m' and h of every component of a union: mk[k], and the heavy flags' prefix
+// hpos at the component's bounds
+__global__ void k_finish_union(int32_t K, const int32_t* __restrict__ off, const int64_t* __restrict__ mk,
+                               const int32_t* __restrict__ hpos, int64_t* __restrict__ acc) {
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+        acc[(int64_t)k * kCountSlots + kMp] = mk[k];
+        acc[(int64_t)k * kCountSlots + kH] = hpos[off[k + 1]] - hpos[off[k]];
     }
 }
 
@@ -992,14 +1099,21 @@ __device__ __forceinline__ int32_t stage_lists(const int2* __restrict__ L, int32
 // (64 kU).  Items are short, so the chain of dependent loads that opens an
 // item (item, row offsets, keys and list descriptors) is issued for the next
 // item while the current one closes.
-template <int DS>
+// Adds a wave's closure count of one component into that component's T_L.
+__device__ __forceinline__ void flush_tl(int64_t* acc, int32_t c, int64_t total, int lane) {
+    if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[(int64_t)c * kCountSlots + kTL], (unsigned long long)total);
+}
+
+// UNION: the graph is a union of components (comp[x] of every vertex), and
+// each item's closures count towards its anchor's component.
+template <int DS, bool UNION>
 __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ items,
                                                       const int32_t* __restrict__ n_items_dev,
                                                       const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
                                                       const int32_t* __restrict__ rpD,
                                                       const unsigned long long* __restrict__ cw,
                                                       const int2* __restrict__ packU, const int2* __restrict__ packD,
-                                                      int64_t* __restrict__ acc) {
+                                                      const int32_t* __restrict__ comp, int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 4 * DS;                                     // buckets of 4 slots, load <= 1/4
     constexpr int ROW = (HS_MAX + 2 * kJL + 1 + 64 * kU + 3) / 4 * 4;  // keeps every row 16-byte aligned
     constexpr int KR = (DS + 63) / 64;                                 // keys per lane
@@ -1016,11 +1130,11 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
     const int64_t n_items = n_items_dev[0];
-    // the opening of item `it`: anchor row (rs, d) and its iterated list (L, cnt)
-    auto header = [&](int64_t it, int32_t& rs, int32_t& d, const int2*& L, int32_t& cnt) {
+    // the opening of item `it`: anchor x, its row (rs, d) and its iterated list (L, cnt)
+    auto header = [&](int64_t it, int32_t& x, int32_t& rs, int32_t& d, const int2*& L, int32_t& cnt) {
         const int2 item = items[it];
         const bool kind_u = item.x >= 0;
-        const int32_t x = kind_u ? item.x : ~item.x;
+        x = kind_u ? item.x : ~item.x;
         rs = rpO[x];
         d = rpO[x + 1] - rs;
         int32_t llen;
@@ -1040,17 +1154,27 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
         load_lists<64>(L, cnt, lane, st, ln);
     };
     int64_t total = 0;
+    int32_t cur = 0;  // component of the closures in total
     if (gw < n_items) {
-        int32_t rs, d, cnt;
+        int32_t xa, rs, d, cnt;
         const int2* L;
         int32_t kv[KR], st[LR], ln[LR];
-        header(gw, rs, d, L, cnt);
+        header(gw, xa, rs, d, L, cnt);
         body(rs, d, L, cnt, kv, st, ln);
+        if (UNION) cur = comp[xa];
         for (int64_t it = gw; it < n_items; it += nw) {
             const bool more = it + nw < n_items;  // wave-uniform
-            int32_t rs2 = 0, d2 = 0, cnt2 = 0;
+            int32_t xa2 = 0, rs2 = 0, d2 = 0, cnt2 = 0;
             const int2* L2 = L;
-            if (more) header(it + nw, rs2, d2, L2, cnt2);
+            if (more) header(it + nw, xa2, rs2, d2, L2, cnt2);
+            if (UNION) {
+                const int32_t c = comp[xa];
+                if (c != cur) {
+                    flush_tl(acc, cur, total, lane);
+                    total = 0;
+                    cur = c;
+                }
+            }
             const int lg = bucket_bits(d);
             const int hs = 4 << lg;
             for (int i = lane; i < hs; i += 64) tab[i] = -1;
@@ -1065,13 +1189,14 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
             if (more) body(rs2, d2, L2, cnt2, kv, st, ln);  // in flight during the closure
             total += close_flat<kU, false, true>(P, D, nl, 0, W, colO, tab, lg, mark, lane);  // wave-uniform
             wave_lds_sync();
+            xa = xa2;
             rs = rs2;
             d = d2;
             L = L2;
             cnt = cnt2;
         }
     }
-    if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTL], (unsigned long long)total);
+    flush_tl(acc, cur, total, lane);
 }
 
 // One block (4 waves) per item for anchors with large out-lists.  The hash
@@ -1079,15 +1204,15 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
 // sees the LDS address space and emits ds_* instructions), or in a global
 // scratch slice per block when they do not fit (GLOBAL = true).  After
 // staging, each wave closes a quarter of the item's positions.
-template <bool GLOBAL>
+template <bool GLOBAL, bool UNION>
 __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ items,
                                                       const int32_t* __restrict__ n_items_dev,
                                                       const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
                                                       const int32_t* __restrict__ rpD,
                                                       const unsigned long long* __restrict__ cw,
                                                       const int2* __restrict__ packU, const int2* __restrict__ packD,
-                                                      int32_t dcap,
-                                                      int32_t* __restrict__ gscratch, int64_t* __restrict__ acc) {
+                                                      int32_t dcap, int32_t* __restrict__ gscratch,
+                                                      const int32_t* __restrict__ comp, int64_t* __restrict__ acc) {
     extern __shared__ __attribute__((aligned(16))) int32_t dyn[];
     __shared__ int32_t red[5];
     // layout: hash table (4 next_pow2(d) <= 4 dcap slots), P (kJL + 1), D (kJL), flags (4 x 64 kU)
@@ -1104,10 +1229,19 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
     for (int k = 0; k < kU; ++k) mark[lane + 64 * k] = 0;  // flags stay zero between super-strips
     const int64_t n_items = n_items_dev[0];
     int64_t total = 0;
+    int32_t cur = 0;  // component of the closures in total
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = items[it];
         const bool kind_u = item.x >= 0;
         const int32_t x = kind_u ? item.x : ~item.x;
+        if (UNION) {
+            const int32_t c = comp[x];  // block-uniform
+            if (c != cur) {
+                flush_tl(acc, cur, total, lane);
+                total = 0;
+                cur = c;
+            }
+        }
         const int32_t rs = rpO[x];
         const int32_t d = rpO[x + 1] - rs;
         const int2* L;
@@ -1131,7 +1265,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         total += close_flat<kU, GLOBAL, false>(P, D, nl, a, b, colO, tab, lg, mark, lane);  // wave-uniform
         __syncthreads();
     }
-    if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTL], (unsigned long long)total);
+    flush_tl(acc, cur, total, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1143,10 +1277,13 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
 // and adds its counts into rank[] (zeroed beforehand)
 constexpr int kRankChunk = 256;
 
+// In a union of components (comp != nullptr) the order is (component, deg,
+// id): each component's heavy vertices take a contiguous range of ranks, in
+// their own (deg, id) order, so U is block diagonal.
 __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev,
                                                      int32_t hmax, const int32_t* __restrict__ degp,
-                                                     int32_t* __restrict__ rank) {
-    __shared__ int32_t kd[256], kx[256];
+                                                     const int32_t* __restrict__ comp, int32_t* __restrict__ rank) {
+    __shared__ int32_t kd[256], kx[256], kc[256];
     const int32_t h = heavy_count(h_dev, hmax);
     // tiles (256 heavy vertices) x (kRankChunk keys), taken with a static
     // stride by a persistent grid sized for the device's h
@@ -1154,17 +1291,22 @@ __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ 
     for (int64_t tile = blockIdx.x; tile < tx * ty; tile += gridDim.x) {  // block-uniform
         const int64_t i = (tile % tx) * 256 + threadIdx.x;
         const int64_t j0 = (tile / tx) * kRankChunk;
-        int32_t x = -1, dx = 0;
-        if (i < h) { x = hlist[i]; dx = degp[x]; }
+        int32_t x = -1, dx = 0, cx = 0;
+        if (i < h) { x = hlist[i]; dx = degp[x]; cx = comp ? comp[x] : 0; }
         const int64_t j1 = min((int64_t)h, j0 + kRankChunk);
         int32_t r = 0;
         for (int64_t jb = j0; jb < j1; jb += 256) {
             const int64_t j = jb + threadIdx.x;
-            if (j < j1) { kx[threadIdx.x] = hlist[j]; kd[threadIdx.x] = degp[kx[threadIdx.x]]; }
+            if (j < j1) {
+                kx[threadIdx.x] = hlist[j];
+                kd[threadIdx.x] = degp[kx[threadIdx.x]];
+                kc[threadIdx.x] = comp ? comp[kx[threadIdx.x]] : 0;
+            }
             __syncthreads();
             const int lim = (int)min((int64_t)256, j1 - jb);
             if (i < h)
-                for (int q = 0; q < lim; ++q) r += rank_below(kd[q], kx[q], dx, x) ? 1 : 0;
+                for (int q = 0; q < lim; ++q)
+                    r += (kc[q] < cx || (kc[q] == cx && rank_below(kd[q], kx[q], dx, x))) ? 1 : 0;
             __syncthreads();
         }
         if (i < h && r) atomicAdd(&rank[i], r);
@@ -1180,6 +1322,12 @@ __global__ void k_heavy_place(const int32_t* __restrict__ hlist, const int32_t* 
         hidx[x] = rank[i];
         horder[rank[i]] = x;
     }
+}
+
+// hs[k] = heavy vertices before component k (the heavy flags' prefix at its start)
+__global__ void k_heavy_starts(int32_t K, const int32_t* __restrict__ off, const int32_t* __restrict__ hpos,
+                               int32_t* __restrict__ hs) {
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k <= K; k += gridDim.x * blockDim.x) hs[k] = hpos[off[k]];
 }
 
 // U[i][j] = 1 and UT[j][i] = 1 for every oriented edge between heavy ranks i < j
@@ -1261,6 +1409,91 @@ constexpr int kHRow = kHK + 16;  // LDS row stride: 16-lane groups of 16-byte re
 // are enumerated column by column (t = J (J + 1) / 2 + I) and dealt to the 8
 // XCDs in contiguous ranges, so blocks of one XCD share the U^T panels of
 // their columns in that XCD's L2.
+// Masked sum of one 128 x 128 macro tile (I, J), I <= J, of C = U U over the
+// k-blocks [128 I, 128 J + 128) (U strictly upper triangular, hp x hp):
+// this thread's share.  As / Bs: the block's LDS staging.
+__device__ __forceinline__ int64_t mfma_tile(const uint8_t* __restrict__ U, const uint8_t* __restrict__ UT,
+                                             int64_t hp, int64_t I, int64_t J, uint8_t* As, uint8_t* Bs) {
+    const int t = threadIdx.x;
+    const int w = t >> 6;
+    const int lane = __lane_id();
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+    const int fr = lane & 31, fk = 16 * (lane >> 5);
+    const int lr = t >> 1, lc = (t & 1) * (kHK / 2);  // staging: row and byte offset of this thread
+    const int64_t row0 = I * kHT, col0 = J * kHT;
+    const uint8_t* ga = U + (row0 + lr) * hp + lc;
+    const uint8_t* gb = UT + (col0 + lr) * hp + lc;
+    v16i c[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) c[i][j] = (v16i){0};
+    const int64_t kend = col0 + kHT;
+    v4i ra[4], rb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        ra[q] = *(const v4i*)(ga + row0 + 16 * q);
+        rb[q] = *(const v4i*)(gb + row0 + 16 * q);
+    }
+    for (int64_t k0 = row0; k0 < kend; k0 += kHK) {
+        __syncthreads();  // the previous step's fragment reads are done
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            *(v4i*)(As + lr * kHRow + lc + 16 * q) = ra[q];
+            *(v4i*)(Bs + lr * kHRow + lc + 16 * q) = rb[q];
+        }
+        __syncthreads();
+        if (k0 + kHK < kend) {  // block-uniform: the next step's loads fly during these MFMAs
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ra[q] = *(const v4i*)(ga + k0 + kHK + 16 * q);
+                rb[q] = *(const v4i*)(gb + k0 + kHK + 16 * q);
+            }
+        }
+#pragma unroll
+        for (int ks = 0; ks < kHK; ks += 32) {
+            v4i af[2], bf[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = *(const v4i*)(As + (wr + 32 * i + fr) * kHRow + ks + fk);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bf[j] = *(const v4i*)(Bs + (wc + 32 * j + fr) * kHRow + ks + fk);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    c[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[i], bf[j], c[i][j], 0, 0, 0);
+        }
+    }
+    int64_t total = 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint8_t* ucol = U + col0 + wc + 32 * j + fr;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int64_t row = row0 + wr + 32 * i + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                total += (int64_t)c[i][j][q] * (int64_t)ucol[row * hp];
+            }
+        }
+    return total;
+}
+
+// T_H = sum over i < j of (U U)[i][j] U[i][j] with U the strictly upper
+// triangular adjacency of the heavy vertices in rank order (each heavy
+// triangle i < k < j once).  One block per 128 x 128 macro tile (I, J), I <= J,
+// of C = U U; because U is strictly upper triangular, only k in
+// [128 I, 128 J + 128) can contribute, and the k-loop covers exactly those
+// k-blocks.  Per step the block stages 128 rows x 128 k-bytes of U (rows of
+// the tile) and of U^T (columns of the tile) in LDS while the next step's
+// global loads are in flight in registers; each wave owns a 64 x 64 quarter as
+// 2 x 2 tiles of v_mfma_i32_32x32x32_i8.  Operand fragments: lane l supplies
+// row (l mod 32) of the A tile and column (l mod 32) of the B tile, 16
+// consecutive k-bytes starting at 16 (l / 32); A and B use the same
+// k-permutation.  The epilogue masks C with U and adds into T_H.  Macro tiles
+// are enumerated column by column (t = J (J + 1) / 2 + I) and dealt to the 8
+// XCDs in contiguous ranges, so blocks of one XCD share the U^T panels of
+// their columns in that XCD's L2.
 __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ U, const uint8_t* __restrict__ UT,
                                                      const int32_t* __restrict__ h_dev, int32_t hmax,
                                                      int64_t* __restrict__ acc) {
@@ -1271,12 +1504,7 @@ __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ 
     const int64_t hp = heavy_pad(h);
     const int64_t nm = hp / kHT;
     const int64_t ntiles = nm * (nm + 1) / 2;
-    const int t = threadIdx.x;
-    const int w = t >> 6;
     const int lane = __lane_id();
-    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
-    const int fr = lane & 31, fk = 16 * (lane >> 5);
-    const int lr = t >> 1, lc = (t & 1) * (kHK / 2);   // staging: row and byte offset of this thread
     const int64_t xcd = blockIdx.x & 7;
     const int64_t per_xcd = gridDim.x >> 3;
     const int64_t chunk = (ntiles + 7) / 8;
@@ -1287,64 +1515,120 @@ __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ 
         while (J * (J + 1) / 2 > tt) --J;
         while ((J + 1) * (J + 2) / 2 <= tt) ++J;
         const int64_t I = tt - J * (J + 1) / 2;
-        const int64_t row0 = I * kHT, col0 = J * kHT;
-        const uint8_t* ga = U + (row0 + lr) * hp + lc;
-        const uint8_t* gb = UT + (col0 + lr) * hp + lc;
-        v16i c[2][2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) c[i][j] = (v16i){0};
-        const int64_t kend = col0 + kHT;
-        v4i ra[4], rb[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            ra[q] = *(const v4i*)(ga + row0 + 16 * q);
-            rb[q] = *(const v4i*)(gb + row0 + 16 * q);
-        }
-        for (int64_t k0 = row0; k0 < kend; k0 += kHK) {
-            __syncthreads();  // the previous step's fragment reads are done
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                *(v4i*)(As + lr * kHRow + lc + 16 * q) = ra[q];
-                *(v4i*)(Bs + lr * kHRow + lc + 16 * q) = rb[q];
-            }
-            __syncthreads();
-            if (k0 + kHK < kend) {  // block-uniform: the next step's loads fly during these MFMAs
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    ra[q] = *(const v4i*)(ga + k0 + kHK + 16 * q);
-                    rb[q] = *(const v4i*)(gb + k0 + kHK + 16 * q);
-                }
-            }
-#pragma unroll
-            for (int ks = 0; ks < kHK; ks += 32) {
-                v4i af[2], bf[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) af[i] = *(const v4i*)(As + (wr + 32 * i + fr) * kHRow + ks + fk);
-#pragma unroll
-                for (int j = 0; j < 2; ++j) bf[j] = *(const v4i*)(Bs + (wc + 32 * j + fr) * kHRow + ks + fk);
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        c[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[i], bf[j], c[i][j], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const uint8_t* ucol = U + col0 + wc + 32 * j + fr;
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int64_t row = row0 + wr + 32 * i + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    total += (int64_t)c[i][j][q] * (int64_t)ucol[row * hp];
-                }
-            }
+        total += mfma_tile(U, UT, hp, I, J, As, Bs);
     }
     total = wave_sum(total);
     if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTH], (unsigned long long)total);
+}
+
+// ---- heavy blocks of a union of components --------------------------------
+// Component c's heavy vertices hold ranks [hs[c], hs[c+1]) and get their own
+// strictly upper-triangular block U_c of pc[c] x pc[c] bytes (pc = the count
+// rounded up to 128) at byte offset boff[c] of U (and of UT).  Row slot q of
+// the rows of all blocks belongs to component c with prow[c] <= q < prow[c+1].
+
+__device__ __forceinline__ int32_t comp_of_slot(const int64_t* __restrict__ pre, int32_t K, int64_t q) {
+    int32_t lo = 0, hi = K - 1;  // largest c with pre[c] <= q
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_heavy_rows_u(int32_t K, const int32_t* __restrict__ hs,
+                                                       const int32_t* __restrict__ pc,
+                                                       const int64_t* __restrict__ prow,
+                                                       const int64_t* __restrict__ boff,
+                                                       const int32_t* __restrict__ horder,
+                                                       const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
+                                                       const int32_t* __restrict__ hidx, uint8_t* __restrict__ U) {
+    __shared__ __attribute__((aligned(16))) uint8_t row[kRowChunk];
+    const int64_t R = prow[K];
+    for (int64_t q = blockIdx.x; q < R; q += gridDim.x) {  // block-uniform
+        const int32_t c = comp_of_slot(prow, K, q);
+        const int64_t i = q - prow[c];
+        const int32_t h = hs[c + 1] - hs[c];
+        const int64_t p = pc[c];
+        const int32_t x = i < h ? horder[hs[c] + i] : 0;
+        const int32_t b = i < h ? rpO[x] : 0;
+        const int32_t e = i < h ? rpO[x + 1] : 0;
+        uint8_t* Uc = U + boff[c];
+        for (int64_t c0 = 0; c0 < p; c0 += kRowChunk) {
+            const int32_t w = (int32_t)min<int64_t>(kRowChunk, p - c0);  // a multiple of 128
+            for (int32_t k = threadIdx.x; k < w / 16; k += 256) reinterpret_cast<int4*>(row)[k] = make_int4(0, 0, 0, 0);
+            __syncthreads();
+            for (int32_t t = b + threadIdx.x; t < e; t += 256) {
+                const int64_t j = (int64_t)(hidx[colO[t]] - hs[c]) - c0;
+                if (j >= 0 && j < w) row[j] = 1;
+            }
+            __syncthreads();
+            int4* out = reinterpret_cast<int4*>(Uc + i * p + c0);
+            for (int32_t k = threadIdx.x; k < w / 16; k += 256) out[k] = reinterpret_cast<const int4*>(row)[k];
+            __syncthreads();
+        }
+    }
+}
+
+// UT_c = U_c transposed, by 64 x 64 byte tiles; tile slot q of all blocks
+// belongs to component c with ptt[c] <= q < ptt[c+1] ((pc/64)^2 per block).
+__global__ void __launch_bounds__(256) k_heavy_transpose_u(int32_t K, const int32_t* __restrict__ pc,
+                                                            const int64_t* __restrict__ ptt,
+                                                            const int64_t* __restrict__ boff,
+                                                            const uint8_t* __restrict__ U, uint8_t* __restrict__ UT) {
+    __shared__ uint8_t tile[64][64 + 4];
+    const int t = threadIdx.x;
+    const int r = t >> 2, cc = (t & 3) * 16;
+    const int64_t Q = ptt[K];
+    for (int64_t q = blockIdx.x; q < Q; q += gridDim.x) {
+        const int32_t c = comp_of_slot(ptt, K, q);
+        const int64_t hp = pc[c];
+        const int64_t T = hp / 64;
+        const int64_t l = q - ptt[c];
+        const int64_t ti = l / T, tj = l % T;
+        const uint8_t* Uc = U + boff[c];
+        uint8_t* UTc = UT + boff[c];
+        const int4 v = *reinterpret_cast<const int4*>(Uc + (ti * 64 + r) * hp + tj * 64 + cc);
+        const uint32_t wv[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tile[r][cc + k] = (uint8_t)(wv[k >> 2] >> (8 * (k & 3)));
+        __syncthreads();
+        uint32_t o[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) o[k >> 2] |= (uint32_t)tile[cc + k][r] << (8 * (k & 3));
+        *reinterpret_cast<int4*>(UTc + (tj * 64 + r) * hp + ti * 64 + cc) =
+            make_int4((int)o[0], (int)o[1], (int)o[2], (int)o[3]);
+        __syncthreads();
+    }
+}
+
+// T_H of every component: the macro tiles (c, I, J) of the blocks with at
+// least three heavy vertices, from a tile list; each tile adds into its
+// component's T_H.
+__global__ void __launch_bounds__(256) k_heavy_mfma_u(int32_t ntiles, const int4* __restrict__ tiles,
+                                                       const int32_t* __restrict__ pc,
+                                                       const int64_t* __restrict__ boff,
+                                                       const uint8_t* __restrict__ U, const uint8_t* __restrict__ UT,
+                                                       int64_t* __restrict__ acc) {
+    __shared__ __attribute__((aligned(16))) uint8_t As[kHT * kHRow];
+    __shared__ __attribute__((aligned(16))) uint8_t Bs[kHT * kHRow];
+    const int lane = __lane_id();
+    int64_t total = 0;
+    int32_t cur = -1;
+    for (int32_t q = blockIdx.x; q < ntiles; q += gridDim.x) {
+        const int4 tl = tiles[q];  // (component, I, J)
+        if (tl.x != cur) {
+            const int64_t tsum = wave_sum(total);
+            if (cur >= 0 && lane == 0 && tsum)
+                atomicAdd((unsigned long long*)&acc[(int64_t)cur * kCountSlots + kTH], (unsigned long long)tsum);
+            total = 0;
+            cur = tl.x;
+        }
+        total += mfma_tile(U + boff[tl.x], UT + boff[tl.x], pc[tl.x], tl.y, tl.z, As, Bs);
+    }
+    const int64_t tsum = wave_sum(total);
+    if (cur >= 0 && lane == 0 && tsum)
+        atomicAdd((unsigned long long*)&acc[(int64_t)cur * kCountSlots + kTH], (unsigned long long)tsum);
 }
 
 }  // namespace
@@ -1386,19 +1670,103 @@ static LightPlan light_plan(int64_t m, int32_t maxd, const CountConfig& cfg) {
 }
 
 
-void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
-                   hipStream_t s, int64_t* acc) {
+// Heavy phase of a union of components: the heavy counts at the component
+// starts are read back (one synchronisation), and each component with at
+// least three heavy vertices gets its own block, ranked (component, deg, id).
+static void count_union_heavy(const tc_graph_s* g, const CountUnion& un, const CountConfig& cfg, hipStream_t s,
+                              int64_t* acc, const DevBuf<int32_t>& heavy, const DevBuf<int32_t>& hpos,
+                              const int32_t* degp, const DevBuf<int32_t>& rpO, const DevBuf<int32_t>& colO) {
+    (void)cfg;
+    const int64_t n = g->n;
+    const int32_t K = un.K;
+    DevBuf<int32_t> hsd((size_t)K + 1, s);
+    TC_LAUNCH("heavy_starts", k_heavy_starts, dim3(ceil_div((int64_t)K + 1, 256)), dim3(256), 0, s, K, un.off,
+              (const int32_t*)hpos.get(), hsd.get());
+    std::vector<int32_t> hs((size_t)K + 1);
+    check_hip(hipMemcpyAsync(hs.data(), hsd.get(), sizeof(int32_t) * hs.size(), hipMemcpyDeviceToHost, s), "heavy starts");
+    check_hip(hipStreamSynchronize(s), "sync");
+    const int64_t H = hs[(size_t)K];
+    std::vector<int32_t> pc((size_t)K);
+    std::vector<int64_t> prow((size_t)K + 1, 0), ptt((size_t)K + 1, 0), boff((size_t)K, 0);
+    std::vector<int4> tiles;
+    int64_t ubytes = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        const int64_t h = hs[(size_t)k + 1] - hs[(size_t)k];
+        const int64_t p = h >= 3 ? heavy_pad(h) : 0;  // blocks of fewer than 3 vertices hold no triangle
+        pc[(size_t)k] = (int32_t)p;
+        boff[(size_t)k] = ubytes;
+        ubytes += p * p;
+        prow[(size_t)k + 1] = prow[(size_t)k] + p;
+        ptt[(size_t)k + 1] = ptt[(size_t)k] + (p / 64) * (p / 64);
+        for (int32_t J = 0; J < p / kHT; ++J)
+            for (int32_t I = 0; I <= J; ++I) tiles.push_back(make_int4(k, I, J, 0));
+    }
+    if (tiles.empty()) return;
+    if (ubytes > ((int64_t)16 << 30)) fail(TC_ERR_OVERFLOW, "heavy blocks of the union exceed 16 GiB: raise the heavy threshold");
+    if (tiles.size() > (size_t)0x7fffffff) fail(TC_ERR_OVERFLOW, "too many heavy tiles");
+    PhaseScope ph("heavy");
+    DevBuf<int32_t> pcd(K, s);
+    DevBuf<int64_t> prowd((size_t)K + 1, s), pttd((size_t)K + 1, s), boffd(K, s);
+    DevBuf<int4> tilesd(tiles.size(), s);
+    check_hip(hipMemcpyAsync(pcd.get(), pc.data(), sizeof(int32_t) * pc.size(), hipMemcpyHostToDevice, s), "pc");
+    check_hip(hipMemcpyAsync(prowd.get(), prow.data(), sizeof(int64_t) * prow.size(), hipMemcpyHostToDevice, s), "prow");
+    check_hip(hipMemcpyAsync(pttd.get(), ptt.data(), sizeof(int64_t) * ptt.size(), hipMemcpyHostToDevice, s), "ptt");
+    check_hip(hipMemcpyAsync(boffd.get(), boff.data(), sizeof(int64_t) * boff.size(), hipMemcpyHostToDevice, s), "boff");
+    check_hip(hipMemcpyAsync(tilesd.get(), tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, s),
+              "tiles");
+    DevBuf<int32_t> hlist(H, s), hidx(n, s), horder(H, s), hrank(H, s);
+    const int32_t hm = (int32_t)H;
+    const int32_t* h_dev = hpos.get() + n;
+    TC_LAUNCH("heavy_list", k_heavy_list, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)heavy.get(),
+              (const int32_t*)hpos.get(), hm, hlist.get(), acc);
+    fill_i32(hrank.get(), 0, H, s);
+    TC_LAUNCH("heavy_rank", k_heavy_rank, dim3((unsigned)std::min<int64_t>(
+                                              (int64_t)ceil_div(H, 256) * (int64_t)ceil_div(H, kRankChunk),
+                                              (int64_t)num_cus() * 4)),
+              dim3(256), 0, s, (const int32_t*)hlist.get(), h_dev, hm, degp, un.comp, hrank.get());
+    TC_LAUNCH("heavy_place", k_heavy_place, dim3(ceil_div(H, 256)), dim3(256), 0, s, (const int32_t*)hlist.get(),
+              h_dev, hm, (const int32_t*)hrank.get(), hidx.get(), horder.get());
+    DevBuf<uint8_t> U((size_t)ubytes, s), UT((size_t)ubytes, s);
+    TC_LAUNCH("heavy_pack", k_heavy_rows_u, dim3((unsigned)std::min<int64_t>(prow[(size_t)K], (int64_t)num_cus() * 8)),
+              dim3(256), 0, s, K, (const int32_t*)hsd.get(), (const int32_t*)pcd.get(), (const int64_t*)prowd.get(),
+              (const int64_t*)boffd.get(), (const int32_t*)horder.get(), (const int32_t*)rpO.get(),
+              (const int32_t*)colO.get(), (const int32_t*)hidx.get(), U.get());
+    TC_LAUNCH("heavy_transpose", k_heavy_transpose_u,
+              dim3((unsigned)std::min<int64_t>(ptt[(size_t)K], (int64_t)num_cus() * 8)), dim3(256), 0, s, K,
+              (const int32_t*)pcd.get(), (const int64_t*)pttd.get(), (const int64_t*)boffd.get(),
+              (const uint8_t*)U.get(), UT.get());
+    TC_LAUNCH("heavy_mfma", k_heavy_mfma_u,
+              dim3((unsigned)std::min<int64_t>((int64_t)tiles.size(), (int64_t)num_cus() * 8)), dim3(256), 0, s,
+              (int32_t)tiles.size(), (const int4*)tilesd.get(), (const int32_t*)pcd.get(), (const int64_t*)boffd.get(),
+              (const uint8_t*)U.get(), (const uint8_t*)UT.get(), acc);
+}
+
+// The count of g (un == nullptr), or of every component of the union graph g
+// (un != nullptr; g unsampled): see count_enqueue and count_union.
+static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
+                       hipStream_t s, int64_t* acc, const CountUnion* un) {
     const int64_t n = g->n;
     const int64_t E2 = 2 * g->m;
     if (cfg.small_dmax > 128 || cfg.small_dmax < 1) fail(TC_ERR_INVALID, "small_dmax must be in [1, 128]");
-    fill_i64(acc, 0, kCountSlots, s);
-    if (n == 0 || E2 == 0) return;
+    const int32_t K = un ? un->K : 1;
+    const int32_t* comp = un ? un->comp : nullptr;
+    fill_i64(acc, 0, (int64_t)K * kCountSlots, s);
+    if (n == 0 || E2 == 0) {
+        if (un && K > 0 && n > 0) {  // m' = 0 and h = 0 for every component
+            DevBuf<int32_t> zero(n + 1, s);
+            fill_i32(zero.get(), 0, n + 1, s);
+            TC_LAUNCH("finish_union", k_finish_union, dim3(ceil_div(K, 256)), dim3(256), 0, s, K, un->off, un->mk,
+                      (const int32_t*)zero.get(), acc);
+        }
+        return;
+    }
     const int64_t NW = (E2 + 63) / 64;
 
-    // host-side bounds for every launch (no read-back inside a count)
-    const int64_t hmax = heavy_bound(n, g->m, cfg.heavy_num, cfg.heavy_den);
-    const int64_t hp_max = heavy_pad(hmax);
-    if (hp_max * hp_max > ((int64_t)16 << 30))
+    // host-side bounds for every launch (no read-back inside a count; a union
+    // reads its heavy count back before the heavy phase instead)
+    int64_t hmax = heavy_bound(n, g->m, cfg.heavy_num, cfg.heavy_den);
+    int64_t hp_max = heavy_pad(hmax);
+    if (!un && hp_max * hp_max > ((int64_t)16 << 30))
         fail(TC_ERR_OVERFLOW, "heavy block bound exceeds 16 GiB: raise the heavy threshold");
     const int64_t items_max = 2 * n + E2 / kJL + 2;
 
@@ -1452,12 +1820,14 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     const int32_t vcap = cfg.vmajor_cap;
     DevBuf<int32_t> heavy(n + 1, s), code(n, s), dminus(n, s), rpD(n + 1, s);
     TC_LAUNCH("vertex_prep", k_vertex_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, n, degp,
-              (const int32_t*)dplus.get(), mp_dev, cfg.heavy_num, cfg.heavy_den, heavy.get(), code.get(),
-              dminus.get());
+              (const int32_t*)dplus.get(), mp_dev, comp, un ? un->mk : (const int64_t*)nullptr, cfg.heavy_num,
+              cfg.heavy_den, heavy.get(), code.get(), dminus.get());
     scan_exclusive_i32(dminus.get(), rpD.get(), n, s);  // slots of each vertex's v-major descriptors
     PhaseScope ph_light("light");
     DevBuf<int4> rowQ(n, s);
     DevBuf<int64_t> Wu(n, s), cw(n, s);
+    DevBuf<int64_t> Gx(un ? n : 0, s);  // per-list gather statistic (unions)
+    int64_t* gxp = un ? Gx.get() : nullptr;
     DevBuf<int2> packD(vcap > 0 ? g->m : 1, s);  // v-major descriptors, rpD[v].. for vertex v
     unsigned long long* cwp = reinterpret_cast<unsigned long long*>(cw.get());
     TC_LAUNCH("row_q", k_row_q, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)rpO.get(),
@@ -1466,7 +1836,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     DevBuf<int32_t> wide(3 * (n + 1), s);  // vertices with d+ in (128, 256], (256, 512], > 512; counts first
     for (int c = 0; c < 3; ++c) fill_i32(wide.get() + c * (n + 1), 0, 1, s);
     TC_LAUNCH("work", k_work_lanes, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int4*)rowQ.get(),
-              colO.get(), vcap, packU.get(), packD.get(), cwp, Wu.get(), wide.get(), acc);
+              colO.get(), vcap, packU.get(), packD.get(), cwp, Wu.get(), gxp, wide.get(), acc);
     // longer lists by register class, persistent grids of one round of
     // resident blocks; max_deg bounds every d+
     auto launch_wide = [&](auto kernel, int c, int32_t lo, const char* name, std::atomic<int>& resident) {
@@ -1479,7 +1849,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         }
         TC_LAUNCH(name, kernel, dim3((unsigned)(num_cus() * r)), dim3(256), 0, s,
                   (const int32_t*)wide.get() + c * (n + 1) + 1, (const int4*)rowQ.get(), colO.get(), vcap,
-                  packU.get(), packD.get(), cwp, Wu.get(), acc);
+                  packU.get(), packD.get(), cwp, Wu.get(), gxp, acc);
     };
     static std::atomic<int> res_w[3];
     launch_wide(k_work_wide<4>, 0, 128, "work_w4", res_w[0]);
@@ -1488,9 +1858,15 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
     DevBuf<int32_t> nsm(n + 1, s), nlg(n + 1, s), nhg(n + 1, s);
     const unsigned cgrid = std::min<unsigned>(grid_for(n, 256), kClassifyBlocks);
     DevBuf<int64_t> cpart((size_t)cgrid * 9, s);
-    TC_LAUNCH("classify", k_classify, dim3(cgrid), dim3(256), 0, s, n, (const int32_t*)code.get(),
-              (const int32_t*)dplus.get(), (const int64_t*)Wu.get(), (const unsigned long long*)cwp,
-              (const int32_t*)rpD.get(), cfg.small_dmax, nsm.get(), nlg.get(), nhg.get(), cpart.get());
+    if (!un)
+        TC_LAUNCH("classify", k_classify, dim3(cgrid), dim3(256), 0, s, n, (const int32_t*)code.get(),
+                  (const int32_t*)dplus.get(), (const int64_t*)Wu.get(), (const unsigned long long*)cwp,
+                  (const int32_t*)rpD.get(), cfg.small_dmax, nsm.get(), nlg.get(), nhg.get(), cpart.get());
+    else
+        TC_LAUNCH("classify", k_classify_union, dim3(cgrid), dim3(256), 0, s, n, comp, (const int32_t*)code.get(),
+                  (const int32_t*)dplus.get(), (const int64_t*)Wu.get(), (const int64_t*)gxp,
+                  (const unsigned long long*)cwp, (const int32_t*)rpD.get(), cfg.small_dmax, nsm.get(), nlg.get(),
+                  nhg.get(), acc);
     DevBuf<int32_t> sbase(n + 1, s), lbase(n + 1, s), hbase(n + 1, s), hpos(n + 1, s);
     {
         const int32_t* in[4] = {nsm.get(), nlg.get(), nhg.get(), heavy.get()};
@@ -1510,16 +1886,18 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
         // blocks in a second round: cap the blocks per CU at the resident count
         static const int resident = [] {
             int r = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_light_small<128>, 256, 0) != hipSuccess || r < 1)
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_light_small<128, false>, 256, 0) != hipSuccess ||
+                r < 1)
                 r = 1;
             (void)hipGetLastError();
             return r;
         }();
         const int64_t blocks = (int64_t)num_cus() * std::min<int32_t>(cfg.light_blocks_per_cu, resident);
-        TC_LAUNCH("light_small", k_light_small<128>, dim3((unsigned)blocks), dim3(256), 0, s,
+        auto kernel = un ? k_light_small<128, true> : k_light_small<128, false>;
+        TC_LAUNCH("light_small", kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                   (const int2*)items.get(), (const int32_t*)sbase.get() + n, (const int32_t*)rpO.get(),
                   (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
-                  (const int2*)packU.get(), (const int2*)packD.get(), acc);
+                  (const int2*)packU.get(), (const int2*)packD.get(), comp, acc);
     }
     auto launch_large = [&](const DevBuf<int32_t>& cnt, const DevBuf<int32_t>& base, int32_t dcap, bool global) {
         DevBuf<int2> items(items_max, s);
@@ -1536,7 +1914,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
             while ((1 << lgc) < dcap) ++lgc;
             int r = resident[lgc].load(std::memory_order_relaxed);
             if (!r) {
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_light_large<false>, 256, lds_bytes) !=
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_light_large<false, false>, 256, lds_bytes) !=
                         hipSuccess || r < 1)
                     r = 1;
                 (void)hipGetLastError();
@@ -1544,25 +1922,31 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
             }
             const int64_t per_cu = std::min(r, 8);
             const int64_t blocks = (int64_t)num_cus() * per_cu;
-            TC_LAUNCH("light_large", k_light_large<false>, dim3((unsigned)blocks), dim3(256), lds_bytes, s,
+            auto kernel = un ? k_light_large<false, true> : k_light_large<false, false>;
+            TC_LAUNCH("light_large", kernel, dim3((unsigned)blocks), dim3(256), lds_bytes, s,
                       (const int2*)items.get(), (const int32_t*)base.get() + n, (const int32_t*)rpO.get(),
                       (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
-                      (const int2*)packU.get(), (const int2*)packD.get(), dcap, (int32_t*)nullptr, acc);
+                      (const int2*)packU.get(), (const int2*)packD.get(), dcap, (int32_t*)nullptr, comp, acc);
         } else {
             const int64_t blocks = (int64_t)num_cus();
             DevBuf<int32_t> gscr((size_t)blocks * per_block, s);
-            TC_LAUNCH("light_huge", k_light_large<true>, dim3((unsigned)blocks), dim3(256), 0, s,
+            auto kernel = un ? k_light_large<true, true> : k_light_large<true, false>;
+            TC_LAUNCH("light_huge", kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                       (const int2*)items.get(), (const int32_t*)base.get() + n, (const int32_t*)rpO.get(),
                       (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
-                      (const int2*)packU.get(), (const int2*)packD.get(), dcap, gscr.get(), acc);
+                      (const int2*)packU.get(), (const int2*)packD.get(), dcap, gscr.get(), comp, acc);
         }
     };
     const LightPlan plan = light_plan(g->m, maxd, cfg);
     if (plan.dcap_lds) launch_large(nlg, lbase, plan.dcap_lds, false);
     if (plan.dcap_global) launch_large(nhg, hbase, plan.dcap_global, true);
 
-    // 5. heavy phase: sized by the bound, trimmed to the device's h inside the kernels
-    if (hmax >= 3) {
+    // 5. heavy phase: sized by the bound, trimmed to the device's h inside the
+    //    kernels (a union: one block per component, sized from the heavy
+    //    counts read back here)
+    if (un) {
+        count_union_heavy(g, *un, cfg, s, acc, heavy, hpos, degp, rpO, colO);
+    } else if (hmax >= 3) {
         PhaseScope ph("heavy");
         DevBuf<int32_t> hlist(hmax, s), hidx(n, s), horder(hmax, s);
         const int32_t* h_dev = hpos.get() + n;
@@ -1575,7 +1959,7 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
                                                   (int64_t)ceil_div(hmax, 256) * (int64_t)ceil_div(hmax, kRankChunk),
                                                   (int64_t)num_cus() * 4)),
                   dim3(256), 0, s,
-                  (const int32_t*)hlist.get(), h_dev, hm, degp, hrank.get());
+                  (const int32_t*)hlist.get(), h_dev, hm, degp, (const int32_t*)nullptr, hrank.get());
         TC_LAUNCH("heavy_place", k_heavy_place, dim3(ceil_div(hmax, 256)), dim3(256), 0, s,
                   (const int32_t*)hlist.get(), h_dev, hm, (const int32_t*)hrank.get(), hidx.get(), horder.get());
         DevBuf<uint8_t> U((size_t)hp_max * hp_max, s), UT((size_t)hp_max * hp_max, s);
@@ -1593,8 +1977,22 @@ void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt
                   (const uint8_t*)UT.get(), h_dev, hm, acc);
     }
     PhaseScope ph_finish("finish");
-    TC_LAUNCH("finish", k_finish, dim3(1), dim3(576), 0, s, mp_dev, (const int32_t*)hpos.get() + n,
-              (const int64_t*)cpart.get(), (int32_t)cgrid, acc);
+    if (!un)
+        TC_LAUNCH("finish", k_finish, dim3(1), dim3(576), 0, s, mp_dev, (const int32_t*)hpos.get() + n,
+                  (const int64_t*)cpart.get(), (int32_t)cgrid, acc);
+    else
+        TC_LAUNCH("finish_union", k_finish_union, dim3(ceil_div(K, 256)), dim3(256), 0, s, K, un->off, un->mk,
+                  (const int32_t*)hpos.get(), acc);
+}
+
+void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
+                   hipStream_t s, int64_t* acc) {
+    count_impl(g, sampled, thr, salt, cfg, s, acc, nullptr);
+}
+
+void count_union(const tc_graph_s* g, const CountUnion& un, const CountConfig& cfg, hipStream_t s, int64_t* acc) {
+    if (un.K < 1 || !un.comp || !un.off || !un.mk) fail(TC_ERR_INVALID, "union descriptor incomplete");
+    count_impl(g, 0, 0, 0, cfg, s, acc, &un);
 }
 
 void counts_from_slots(const int64_t* hacc, tc_counts* out) {
@@ -1643,6 +2041,23 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
         const int64_t hp = heavy_pad(hmax);
         b += 3 * rb(4 * hmax) + rb(4 * n) + 2 * rb(hp * hp);  // list, order, rank, index, U, UT
     }
+    return b;
+}
+
+int64_t count_union_bytes(int64_t n, int64_t m, int32_t maxd, int32_t K, int64_t h, int64_t ubytes, int64_t ntiles,
+                          const CountConfig& cfg) {
+    auto rb = region_bytes;
+    // the single count's allocations without its heavy phase
+    int64_t b = count_bytes(n, m, maxd, 0, cfg) - rb(8 * kCountSlots);
+    const int64_t hb = heavy_bound(n, m, cfg.heavy_num, cfg.heavy_den);
+    if (n > 0 && m > 0 && hb >= 3) {
+        const int64_t hp = heavy_pad(hb);
+        b -= 3 * rb(4 * hb) + rb(4 * n) + 2 * rb(hp * hp);
+    }
+    b += rb(8 * n) + rb(4 * (n + 1));  // per-list gather statistic; the zero row of an edgeless union
+    // heavy blocks: starts, block sizes and offsets, tile list, ranks, two matrices
+    b += rb(4 * ((int64_t)K + 1)) + rb(4 * (int64_t)K) + 2 * rb(8 * ((int64_t)K + 1)) + rb(8 * (int64_t)K) +
+         rb(16 * ntiles) + 3 * rb(4 * h) + rb(4 * n) + 2 * rb(ubytes);
     return b;
 }
 

@@ -208,6 +208,48 @@ constexpr int kCountSlots = 16;
 // lands in acc[kCountSlots] (device).  Launch sizes come from host-side bounds.
 void count_enqueue(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t salt, const CountConfig& cfg,
                    hipStream_t s, int64_t* acc);
+
+// A graph that is the disjoint union of K components (independent samples of
+// one graph, or several requests' graphs): vertex x belongs to component
+// comp[x], component k owns the vertices [off[k], off[k+1]) and every off[k]
+// is a multiple of kUnionAlign, so that aligned vertex windows of the count
+// kernels never straddle two components.  mk[k] = edges of component k.  All
+// arrays are device arrays.
+constexpr int kUnionAlign = 256;
+struct CountUnion {
+    int32_t K = 1;
+    const int32_t* comp = nullptr;  // [n]
+    const int32_t* off = nullptr;   // [K + 1]
+    const int64_t* mk = nullptr;    // [K]
+};
+
+// The exact count of every component of the (unsampled) union graph g with
+// one pass of the count's kernels: component k's results land in
+// acc[k * kCountSlots ..] (device, K * kCountSlots slots), equal to a count of
+// that component alone.  Synchronises s once (to size the heavy block).
+void count_union(const tc_graph_s* g, const CountUnion& un, const CountConfig& cfg, hipStream_t s, int64_t* acc);
+// An upper bound of the sum of the sizes of every allocation count_union
+// makes for a union of K components, n vertices, m edges, maximum degree maxd,
+// at most h heavy vertices in all, heavy blocks of at most ubytes bytes and at
+// most ntiles macro tiles.
+int64_t count_union_bytes(int64_t n, int64_t m, int32_t maxd, int32_t K, int64_t h, int64_t ubytes, int64_t ntiles,
+                          const CountConfig& cfg);
+
+// Union of K independent samples of g (keep probability thr, salts[k] device
+// array): component k is g sampled with salts[k], its vertex x is union vertex
+// k * n_pad + x (n_pad = n rounded up to kUnionAlign).  Builds the union's CSR
+// into *out (allocations through dev_alloc, released by graph_release) and
+// the comp / off / mk arrays (owned by the caller's buffers: comp[K * n_pad],
+// off[K + 1], mk[K]).  Synchronises s once (to size the sampled CSR).
+void sample_union_replicas(const tc_graph_s* g, int32_t K, const uint64_t* salts, uint64_t thr, hipStream_t s,
+                           tc_graph_s* out, int32_t* comp, int32_t* off, int64_t* mk);
+// Union of the components of the graph gU (vertex ranges off[k]..off[k+1]
+// given in comp / off, device), component k sampled with (thrs[k], salts[k])
+// on its local ids x - off[k]; writes the sampled CSR to *out and mk.
+// Synchronises s once.
+void sample_union_components(const tc_graph_s* gU, int32_t K, const int32_t* comp, const int32_t* off,
+                             const uint64_t* salts, const uint64_t* thrs, hipStream_t s, tc_graph_s* out,
+                             int64_t* mk);
 void counts_from_slots(const int64_t* hacc, tc_counts* out);
 // Sum of the sizes of every allocation count_core makes (region_bytes each) on
 // a graph of n vertices, m edges and maximum degree maxd.
