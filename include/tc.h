@@ -268,15 +268,24 @@ const char* tc_last_error(void);
      installed allocator; nothing is allocated from the device while serving.
    - Lanes: each lane is a host worker thread with its own stream (default
      priority).  lanes = 1 serves one request at a time in arrival order.
+   - Fusion (fuse_max_pairs > 0): a group of small requests is admitted as one
+     reservation (the sum bound of the group's union build and count) and
+     its requests complete together; reserved_bytes and peak_bytes of each
+     result are the group's.
    - Results equal those of tc_build_csr + tc_estimate with the same (p, seed)
      and default tc_params, bit for bit, whatever else is in flight.
    - Thread safety: every tc_server_* call may come from any thread. */
 typedef struct tc_server_s* tc_server;
 
 typedef struct {
-    int64_t budget_bytes;  /* device arena size (rounded down to 256 B); 0 admits nothing */
-    int32_t lanes;         /* concurrent requests, 1..16 */
-    int32_t reserved;      /* must be 0 */
+    int64_t budget_bytes;   /* device arena size (rounded down to 256 B); 0 admits nothing */
+    int32_t lanes;          /* concurrent requests, 1..16 */
+    int32_t fuse_max_pairs; /* 0: every request runs alone.  > 0: a request given as pairs with at most
+                               this many pairs is fused with the released requests of the same kind
+                               queued right behind it (at most 64, at most 8 x fuse_max_pairs pairs in
+                               all): their graphs are built as one disjoint union and counted by one
+                               pass of the kernels, each request sampled with its own (p, seed) and
+                               counted into its own results, bit-identical to running it alone */
 } tc_server_config;
 
 typedef struct {

@@ -256,12 +256,13 @@ def tc_request_bytes(p, graph=None, n=0, src=None, dst=None):
 
 
 class Server:
-    """Serving engine (``tc_server_*``): a device arena of ``budget_bytes`` and
-    ``lanes`` concurrent requests.  Host arrays and graphs of submitted
+    """Serving engine (``tc_server_*``): a device arena of ``budget_bytes``,
+    ``lanes`` concurrent requests, and requests of at most ``fuse_max_pairs``
+    pairs fused with the small ones queued behind them (0: never).  Host arrays and graphs of submitted
     requests are kept referenced here until their results are polled."""
 
-    def __init__(self, budget_bytes, lanes=4):
-        cfg = TcServerConfig(int(budget_bytes), int(lanes), 0)
+    def __init__(self, budget_bytes, lanes=4, fuse_max_pairs=0):
+        cfg = TcServerConfig(int(budget_bytes), int(lanes), int(fuse_max_pairs))
         h = ctypes.c_void_p(0)
         check(_native.load().tc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

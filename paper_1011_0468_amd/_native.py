@@ -52,7 +52,7 @@ class TcTripleResult(ctypes.Structure):
 
 
 class TcServerConfig(ctypes.Structure):
-    _fields_ = [("budget_bytes", ctypes.c_int64), ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("lanes", ctypes.c_int32), ("fuse_max_pairs", ctypes.c_int32)]
 
 
 class TcRequest(ctypes.Structure):

@@ -509,7 +509,7 @@ static void count_batch(const tc_graph_s* g, int sampled, uint64_t thr, const ui
     if (kc < 1) kc = 1;
     for (int32_t i0 = 0; i0 < S; i0 += (int32_t)kc) {
         const int32_t K = (int32_t)std::min<int64_t>(kc, S - i0);
-        if (K == 1) {
+        if (K == 1) {  // a union of one costs two synchronisations and saves nothing
             count_core(g, sampled, thr, salts[i0], cfg, s, &res[(size_t)i0]);
             continue;
         }

@@ -212,10 +212,12 @@ __global__ void k_vertex_prep(int64_t n, const int32_t* __restrict__ degp, const
 // rowQ[x] = (start of N+(x), code ? d+ : ~d+, deg, 0): everything the anchor
 // work needs of a vertex in one 16-byte load; cw[x] = rpD[x] << 32, the first
 // slot of x's v-major descriptors (see claim_vmajor)
+// (also clears the counts of the three wide-list classes, wide[c * (n + 1)])
 __global__ void k_row_q(int64_t n, const int32_t* __restrict__ rpO, const int32_t* __restrict__ code,
                         const int32_t* __restrict__ dplus, const int32_t* __restrict__ degp,
                         const int32_t* __restrict__ rpD, int4* __restrict__ rowQ,
-                        unsigned long long* __restrict__ cw) {
+                        unsigned long long* __restrict__ cw, int32_t* __restrict__ wide) {
+    if (blockIdx.x == 0 && threadIdx.x < 3) wide[threadIdx.x * (n + 1)] = 0;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = code[x];
         rowQ[x] = make_int4(rpO[x], c ? c : ~dplus[x], degp[x], 0);
@@ -734,13 +736,21 @@ __global__ void __launch_bounds__(256) k_classify_union(int64_t n, const int32_t
 
 // items of anchor x: (x, r) for the u-major ranges r of N+(x), then (~x, r)
 // for the ranges r of x's v-major descriptors
-__global__ void k_items(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ base,
+// The item lists of all three bins in one pass: an anchor's items go to the
+// list of its bin (small, large or huge, exclusive) at its bin's prefix.
+__global__ void k_items(int64_t n, const int32_t* __restrict__ nsm, const int32_t* __restrict__ nlg,
+                        const int32_t* __restrict__ nhg, const int32_t* __restrict__ sbase,
+                        const int32_t* __restrict__ lbase, const int32_t* __restrict__ hbase,
                         const int32_t* __restrict__ dplus, const int64_t* __restrict__ Wu,
                         const unsigned long long* __restrict__ cw, const int32_t* __restrict__ rpD,
-                        int2* __restrict__ items) {
+                        int2* __restrict__ items_s, int2* __restrict__ items_l, int2* __restrict__ items_h) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-        if (cnt[x] == 0) continue;
-        int32_t b = base[x];
+        int2* items;
+        int32_t b;
+        if (nsm[x]) { items = items_s; b = sbase[x]; }
+        else if (nlg[x]) { items = items_l; b = lbase[x]; }
+        else if (nhg[x]) { items = items_h; b = hbase[x]; }
+        else continue;
         const int32_t cu = items_of(Wu[x], dplus[x]);
         const unsigned long long c2 = cw[x];
         const int32_t cv = items_of(cw_len(c2), cw_end(c2) - rpD[x]);
@@ -1826,15 +1836,14 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     PhaseScope ph_light("light");
     DevBuf<int4> rowQ(n, s);
     DevBuf<int64_t> Wu(n, s), cw(n, s);
+    DevBuf<int32_t> wide(3 * (n + 1), s);  // vertices with d+ in (128, 256], (256, 512], > 512; counts first
     DevBuf<int64_t> Gx(un ? n : 0, s);  // per-list gather statistic (unions)
     int64_t* gxp = un ? Gx.get() : nullptr;
     DevBuf<int2> packD(vcap > 0 ? g->m : 1, s);  // v-major descriptors, rpD[v].. for vertex v
     unsigned long long* cwp = reinterpret_cast<unsigned long long*>(cw.get());
     TC_LAUNCH("row_q", k_row_q, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)rpO.get(),
               (const int32_t*)code.get(), (const int32_t*)dplus.get(), degp, (const int32_t*)rpD.get(), rowQ.get(),
-              cwp);
-    DevBuf<int32_t> wide(3 * (n + 1), s);  // vertices with d+ in (128, 256], (256, 512], > 512; counts first
-    for (int c = 0; c < 3; ++c) fill_i32(wide.get() + c * (n + 1), 0, 1, s);
+              cwp, wide.get());
     TC_LAUNCH("work", k_work_lanes, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int4*)rowQ.get(),
               colO.get(), vcap, packU.get(), packD.get(), cwp, Wu.get(), gxp, wide.get(), acc);
     // longer lists by register class, persistent grids of one round of
@@ -1877,11 +1886,17 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     // 4. light phase: three bins by anchor out-degree; each kernel is a
     //    persistent grid that reads its item count from device memory
     const int32_t maxd = g->max_deg;  // bounds every d+ of every sample
+    const LightPlan plan = light_plan(g->m, maxd, cfg);
+    // the item lists of the launched bins (a bin that is not launched has no items)
+    DevBuf<int2> items_s(items_max, s), items_l(plan.dcap_lds ? items_max : 0, s),
+        items_h(plan.dcap_global ? items_max : 0, s);
+    TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)nsm.get(),
+              (const int32_t*)nlg.get(), (const int32_t*)nhg.get(), (const int32_t*)sbase.get(),
+              (const int32_t*)lbase.get(), (const int32_t*)hbase.get(), (const int32_t*)dplus.get(),
+              (const int64_t*)Wu.get(), (const unsigned long long*)cwp, (const int32_t*)rpD.get(), items_s.get(),
+              items_l.get(), items_h.get());
     {
-        DevBuf<int2> items(items_max, s);
-        TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)nsm.get(),
-                  (const int32_t*)sbase.get(), (const int32_t*)dplus.get(), (const int64_t*)Wu.get(),
-                  (const unsigned long long*)cwp, (const int32_t*)rpD.get(), items.get());
+        const DevBuf<int2>& items = items_s;
         // a persistent grid larger than what stays resident would run its last
         // blocks in a second round: cap the blocks per CU at the resident count
         static const int resident = [] {
@@ -1899,11 +1914,7 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
                   (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
                   (const int2*)packU.get(), (const int2*)packD.get(), comp, acc);
     }
-    auto launch_large = [&](const DevBuf<int32_t>& cnt, const DevBuf<int32_t>& base, int32_t dcap, bool global) {
-        DevBuf<int2> items(items_max, s);
-        TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)cnt.get(),
-                  (const int32_t*)base.get(), (const int32_t*)dplus.get(), (const int64_t*)Wu.get(),
-                  (const unsigned long long*)cwp, (const int32_t*)rpD.get(), items.get());
+    auto launch_large = [&](const DevBuf<int2>& items, const DevBuf<int32_t>& base, int32_t dcap, bool global) {
         // tab: 4 * next_pow2(d) <= 4 * dcap slots, P: kJL+1, D: kJL, flags: 4*64*kU (16-byte multiple)
         const size_t per_block = (size_t)large_block_words(dcap);
         const size_t lds_bytes = sizeof(int32_t) * per_block;
@@ -1937,9 +1948,8 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
                       (const int2*)packU.get(), (const int2*)packD.get(), dcap, gscr.get(), comp, acc);
         }
     };
-    const LightPlan plan = light_plan(g->m, maxd, cfg);
-    if (plan.dcap_lds) launch_large(nlg, lbase, plan.dcap_lds, false);
-    if (plan.dcap_global) launch_large(nhg, hbase, plan.dcap_global, true);
+    if (plan.dcap_lds) launch_large(items_l, lbase, plan.dcap_lds, false);
+    if (plan.dcap_global) launch_large(items_h, hbase, plan.dcap_global, true);
 
     // 5. heavy phase: sized by the bound, trimmed to the device's h inside the
     //    kernels (a union: one block per component, sized from the heavy
@@ -2034,8 +2044,8 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     const int64_t items_max = 2 * n + E2 / kJL + 2;
     b += rb(8 * items_max);
     const LightPlan plan = light_plan(m, maxd, cfg);
-    if (plan.dcap_lds) b += rb(8 * items_max);
-    if (plan.dcap_global) b += rb(8 * items_max) + rb(4 * (int64_t)num_cus() * large_block_words(plan.dcap_global));
+    b += plan.dcap_lds ? rb(8 * items_max) : rb(8);
+    b += plan.dcap_global ? rb(8 * items_max) + rb(4 * (int64_t)num_cus() * large_block_words(plan.dcap_global)) : rb(8);
     const int64_t hmax = heavy_bound(n, m, cfg.heavy_num, cfg.heavy_den);
     if (hmax >= 3) {
         const int64_t hp = heavy_pad(hmax);

@@ -247,6 +247,8 @@ void sample_union_replicas(const tc_graph_s* g, int32_t K, const uint64_t* salts
 // given in comp / off, device), component k sampled with (thrs[k], salts[k])
 // on its local ids x - off[k]; writes the sampled CSR to *out and mk.
 // Synchronises s once.
+// comp[x] for x < n from the component starts off[K + 1] (device)
+void comp_from_offsets(int64_t n, int32_t K, const int32_t* off, int32_t* comp, hipStream_t s);
 void sample_union_components(const tc_graph_s* gU, int32_t K, const int32_t* comp, const int32_t* off,
                              const uint64_t* salts, const uint64_t* thrs, hipStream_t s, tc_graph_s* out,
                              int64_t* mk);

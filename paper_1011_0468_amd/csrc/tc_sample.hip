@@ -161,27 +161,63 @@ __global__ void k_rows_rep(const int32_t* __restrict__ row_ptr, int64_t n, int64
     }
 }
 
-// Kept entries of the replicated space, relabelled to union vertex ids.
+// The id of union vertex x after dropping the isolated ones:
+// nzt[x / 64].z + (the kept vertices below x in its 64-vertex word), from one
+// 16-byte gather (see k_nz_table).
+__device__ __forceinline__ int32_t nz_id(const int4* __restrict__ nzt, int64_t x) {
+    const int4 t = nzt[x >> 6];
+    const uint64_t b = ((uint64_t)(uint32_t)t.y << 32) | (uint32_t)t.x;
+    const int r = (int)(x & 63);
+    return t.z + __popcll(r == 0 ? 0ull : (b & (~0ull >> (64 - r))));
+}
+
+// Kept entries of the replicated space, in the padded layout's ids (k_nz_relabel
+// maps them to the union's final ids).  One wave per word of g for every
+// copy, so each entry of g is read once; the copies' keep words and prefixes
+// are loaded 64 at a time, one copy per lane, and taken with readlane.
 __global__ void __launch_bounds__(256) k_compact_rep(const int32_t* __restrict__ col, const int32_t* __restrict__ src,
                                                       int64_t E2, int64_t NWp, int32_t K, int64_t npad,
                                                       const uint64_t* __restrict__ bits,
                                                       const int32_t* __restrict__ wpre, int32_t* __restrict__ col_out,
                                                       int32_t* __restrict__ src_out) {
     const int lane = __lane_id();
-    const int64_t nw = (int64_t)K * NWp;
     const uint64_t below = lanes_below();
     const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t w = wave; w < nw; w += nwaves) {
-        const uint64_t bw = bits[w];
-        if (!bw) continue;  // wave-uniform
-        const int64_t k = w / NWp;
-        const int64_t e = (w - k * NWp) * 64 + lane;
-        if ((bw >> lane) & 1ull) {  // set bits lie below E2
-            const int32_t p = wpre[w] + __popcll(bw & below);
-            col_out[p] = (int32_t)(k * npad + col[e]);
-            src_out[p] = (int32_t)(k * npad + src[e]);
+    for (int64_t w = wave; w < NWp; w += nwaves) {
+        const int64_t e = w * 64 + lane;
+        const bool in = e < E2;
+        const int32_t v = in ? col[e] : 0, u = in ? src[e] : 0;
+        for (int32_t k0 = 0; k0 < K; k0 += 64) {
+            const int32_t kl = k0 + lane;
+            const int64_t wl = (int64_t)kl * NWp + w;
+            const uint64_t myb = kl < K ? bits[wl] : 0ull;
+            const int32_t myp = kl < K ? wpre[wl] : 0;
+            uint64_t any = ballot64(myb != 0);
+            while (any) {  // copies whose word keeps something, in order
+                const int j = __builtin_ctzll(any);
+                any &= any - 1;
+                const uint64_t bw = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(myb >> 32), j) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)myb, j);
+                const int32_t pre = __builtin_amdgcn_readlane(myp, j);
+                const int64_t k = k0 + j;
+                if ((bw >> lane) & 1ull) {  // set bits lie below E2
+                    const int32_t p = pre + __popcll(bw & below);
+                    col_out[p] = (int32_t)(k * npad + v);
+                    src_out[p] = (int32_t)(k * npad + u);
+                }
+            }
         }
+    }
+}
+
+// the kept entries' padded-layout ids mapped to the union's final ids
+__global__ void k_nz_relabel(int64_t E, const int4* __restrict__ nzt, int32_t* __restrict__ col,
+                             int32_t* __restrict__ src) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = col[e], r = src[e];
+        col[e] = nz_id(nzt, c);
+        src[e] = nz_id(nzt, r);
     }
 }
 
@@ -208,6 +244,107 @@ __global__ void __launch_bounds__(256) k_keep_comp(const int32_t* __restrict__ s
             bits[e >> 6] = b;
             wcnt[e >> 6] = __popcll(b);
         }
+    }
+}
+
+// ---- dropping the isolated vertices of a union of samples -----------------
+// A vertex without kept edges takes part in no triangle and in no statistic
+// of the count, and an order-preserving relabelling keeps the (deg, id)
+// order, so the union keeps only the vertices of degree > 0: component k's
+// nz[k] of them take new ids off'[k] .. off'[k] + nz[k] - 1 in their old
+// order, and off'[k + 1] = off'[k] + nz[k] rounded up to kUnionAlign.
+
+// one bit per union vertex (degree > 0), per-word counts
+__global__ void __launch_bounds__(256) k_nz_bits(int64_t nU, const int32_t* __restrict__ deg, uint64_t* __restrict__ nzb,
+                                                  int32_t* __restrict__ nzc) {
+    const int lane = __lane_id();
+    const int64_t nw = (nU + 63) / 64;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t w = wave; w < nw; w += nwaves) {
+        const int64_t x = w * 64 + lane;
+        const uint64_t b = ballot64(x < nU && deg[x] > 0);
+        if (lane == 0) {
+            nzb[w] = b;
+            nzc[w] = __popcll(b);
+        }
+    }
+}
+
+// new component offsets (one thread; K is small): off2[k], off2[K] = new n
+__global__ void k_nz_offsets(int32_t K, int64_t npad, const int32_t* __restrict__ nzpre, int32_t* __restrict__ off2) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t o = 0;
+    const int64_t wpc = npad / 64;  // words per component
+    for (int32_t k = 0; k < K; ++k) {
+        off2[k] = (int32_t)o;
+        const int64_t nz = (int64_t)nzpre[(k + 1) * wpc] - (int64_t)nzpre[k * wpc];
+        o += (nz + kUnionAlign - 1) / kUnionAlign * kUnionAlign;
+    }
+    off2[K] = (int32_t)o;
+}
+
+// new id of union vertex x (degree > 0)
+__device__ __forceinline__ int32_t nz_newid(int64_t x, int64_t npad, const uint64_t* __restrict__ nzb,
+                                            const int32_t* __restrict__ nzpre, const int32_t* __restrict__ off2) {
+    const int64_t k = x / npad;
+    const int64_t w = x >> 6;
+    const int r = (int)(x & 63);
+    const uint64_t below = r == 0 ? 0ull : (nzb[w] & (~0ull >> (64 - r)));
+    return off2[k] + (nzpre[w] - nzpre[k * (npad / 64)]) + __popcll(below);
+}
+
+// row offsets, degrees and components of the kept vertices at their new ids;
+// the padding slots after each component's vertices get its end offset
+__global__ void k_nz_place(int64_t nU, int64_t npad, int32_t K, const int32_t* __restrict__ rp,
+                           const int32_t* __restrict__ deg, const uint64_t* __restrict__ nzb,
+                           const int32_t* __restrict__ nzpre, const int32_t* __restrict__ off2,
+                           int32_t* __restrict__ rp2, int32_t* __restrict__ deg2, int32_t* __restrict__ comp2) {
+    const int64_t nU2 = off2[K];
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < nU; x += (int64_t)gridDim.x * blockDim.x) {
+        if (deg[x] > 0) {
+            const int32_t y = nz_newid(x, npad, nzb, nzpre, off2);
+            rp2[y] = rp[x];
+            deg2[y] = deg[x];
+            comp2[y] = (int32_t)(x / npad);
+        }
+    }
+    // padding slots: from each component's last kept vertex to the next component
+    for (int64_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t wpc = npad / 64;
+        const int64_t nz = (int64_t)nzpre[(k + 1) * wpc] - (int64_t)nzpre[k * wpc];
+        const int32_t end = rp[(k + 1) * npad];
+        for (int64_t y = off2[k] + nz; y < off2[k + 1]; ++y) {
+            rp2[y] = end;
+            deg2[y] = 0;
+            comp2[y] = (int32_t)k;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) rp2[nU2] = rp[nU];
+}
+
+// nzt[w] = (keep-vertex bits of union vertices 64 w .. 64 w + 63, new id of
+// the first kept vertex at or after 64 w), for the relabelling gathers
+__global__ void k_nz_table(int64_t NV, int64_t npad, const uint64_t* __restrict__ nzb,
+                           const int32_t* __restrict__ nzpre, const int32_t* __restrict__ off2, int4* __restrict__ nzt) {
+    const int64_t wpc = npad / 64;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < NV; w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = w / wpc;
+        const uint64_t b = nzb[w];
+        nzt[w] = make_int4((int32_t)(uint32_t)b, (int32_t)(uint32_t)(b >> 32),
+                           (int32_t)(off2[k] + nzpre[w] - nzpre[k * wpc]), 0);
+    }
+}
+
+// comp[x] = the k with off[k] <= x < off[k + 1] (largest such k)
+__global__ void k_comp_from_off(int64_t n, int32_t K, const int32_t* __restrict__ off, int32_t* __restrict__ comp) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = K - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= x) lo = mid; else hi = mid - 1;
+        }
+        comp[x] = lo;
     }
 }
 
@@ -275,37 +412,71 @@ void sample_union_replicas(const tc_graph_s* g, int32_t K, const uint64_t* salts
     const int64_t NW = (int64_t)K * NWp;
     if (nU > 0x7fffffffLL || NW * 64 > 0x7fffffffLL) fail(TC_ERR_OVERFLOW, "the union of the samples exceeds int32 ids");
     PhaseScope ph("sample");
-    out->n = nU;
     out->home = s;
     out->max_deg = g->max_deg;  // sampled degrees never exceed the graph's
-    out->row_ptr = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(nU + 1), s);
-    out->deg = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(nU > 0 ? nU : 1), s);
-    TC_LAUNCH("comp_rep", k_comp_rep, dim3(grid_for(nU > K + 1 ? nU : K + 1, 256)), dim3(256), 0, s, npad, K, comp, off);
-    int32_t total = 0;
-    if (NW > 0) {
-        DevBuf<uint64_t> bits(NW, s);
-        DevBuf<int32_t> wpre(NW + 1, s);
-        TC_LAUNCH("keep_rep", k_keep_rep, dim3(grid_for(NWp, 4)), dim3(256), 0, s, (const int32_t*)g->src,
-                  (const int32_t*)g->col, E2, NWp, K, salts, thr, bits.get(), wpre.get());
-        scan_exclusive_i32(wpre.get(), wpre.get(), NW, s);
-        TC_LAUNCH("rows_rep", k_rows_rep, dim3(grid_for(nU + 1, 256)), dim3(256), 0, s, (const int32_t*)g->row_ptr, n,
-                  npad, E2, NWp, K, (const uint64_t*)bits.get(), (const int32_t*)wpre.get(), out->row_ptr, out->deg);
-        total = read_total(wpre.get() + NW, s);
-        out->m = total / 2;
-        out->col = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(total > 0 ? total : 1), s);
-        out->src = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(total > 0 ? total : 1), s);
-        TC_LAUNCH("compact_rep", k_compact_rep, dim3(grid_for(NW, 4)), dim3(256), 0, s, (const int32_t*)g->col,
-                  (const int32_t*)g->src, E2, NWp, K, npad, (const uint64_t*)bits.get(), (const int32_t*)wpre.get(),
-                  out->col, out->src);
-    } else {
+    if (NW == 0 || nU == 0) {  // no entries: every component is empty
+        TC_LAUNCH("comp_rep", k_comp_rep, dim3(grid_for(nU > K + 1 ? nU : K + 1, 256)), dim3(256), 0, s, npad, K, comp,
+                  off);
+        out->n = nU;
+        out->row_ptr = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(nU + 1), s);
+        out->deg = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(nU > 0 ? nU : 1), s);
         fill_i32(out->row_ptr, 0, nU + 1, s);
         if (nU > 0) fill_i32(out->deg, 0, nU, s);
         out->m = 0;
         out->col = (int32_t*)dev_alloc(sizeof(int32_t), s);
         out->src = (int32_t*)dev_alloc(sizeof(int32_t), s);
+        TC_LAUNCH("comp_edges", k_comp_edges, dim3(ceil_div(K, 256)), dim3(256), 0, s, K, (const int32_t*)off,
+                  (const int32_t*)out->row_ptr, mk);
+        return;
     }
+    // 1. keep bits of every copy, their scan, the union's rows in the padded layout
+    DevBuf<uint64_t> bits(NW, s);
+    DevBuf<int32_t> wpre(NW + 1, s);
+    TC_LAUNCH("keep_rep", k_keep_rep, dim3(grid_for(NWp, 4)), dim3(256), 0, s, (const int32_t*)g->src,
+              (const int32_t*)g->col, E2, NWp, K, salts, thr, bits.get(), wpre.get());
+    scan_exclusive_i32(wpre.get(), wpre.get(), NW, s);
+    DevBuf<int32_t> rp(nU + 1, s), deg(nU, s);
+    TC_LAUNCH("rows_rep", k_rows_rep, dim3(grid_for(nU + 1, 256)), dim3(256), 0, s, (const int32_t*)g->row_ptr, n, npad,
+              E2, NWp, K, (const uint64_t*)bits.get(), (const int32_t*)wpre.get(), rp.get(), deg.get());
+    // 2. the vertices of degree > 0 and the components' new offsets
+    const int64_t NV = nU / 64;  // nU is a multiple of kUnionAlign
+    DevBuf<uint64_t> nzb(NV, s);
+    DevBuf<int32_t> nzpre(NV + 1, s);
+    TC_LAUNCH("nz_bits", k_nz_bits, dim3(grid_for(NV, 4)), dim3(256), 0, s, nU, (const int32_t*)deg.get(), nzb.get(),
+              nzpre.get());
+    scan_exclusive_i32(nzpre.get(), nzpre.get(), NV, s);
+    TC_LAUNCH("nz_offsets", k_nz_offsets, dim3(1), dim3(64), 0, s, K, npad, (const int32_t*)nzpre.get(), off);
+    int32_t sizes[2] = {0, 0};  // 2m' of the union, new vertex count
+    check_hip(hipMemcpyAsync(&sizes[0], wpre.get() + NW, sizeof(int32_t), hipMemcpyDeviceToHost, s), "sample total");
+    check_hip(hipMemcpyAsync(&sizes[1], off + K, sizeof(int32_t), hipMemcpyDeviceToHost, s), "union vertices");
+    check_hip(hipStreamSynchronize(s), "sync");
+    const int64_t total = sizes[0], nU2 = sizes[1];
+    // 3. the compacted union: rows at the new ids, kept entries relabelled
+    out->n = nU2;
+    out->m = total / 2;
+    out->row_ptr = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(nU2 + 1), s);
+    out->deg = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(nU2 > 0 ? nU2 : 1), s);
+    out->col = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(total > 0 ? total : 1), s);
+    out->src = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)(total > 0 ? total : 1), s);
+    TC_LAUNCH("nz_place", k_nz_place, dim3(grid_for(nU, 256)), dim3(256), 0, s, nU, npad, K, (const int32_t*)rp.get(),
+              (const int32_t*)deg.get(), (const uint64_t*)nzb.get(), (const int32_t*)nzpre.get(), (const int32_t*)off,
+              out->row_ptr, out->deg, comp);
+    DevBuf<int4> nzt(NV, s);
+    TC_LAUNCH("nz_table", k_nz_table, dim3(grid_for(NV, 256)), dim3(256), 0, s, NV, npad, (const uint64_t*)nzb.get(),
+              (const int32_t*)nzpre.get(), (const int32_t*)off, nzt.get());
+    TC_LAUNCH("compact_rep", k_compact_rep, dim3(grid_for(NWp, 4)), dim3(256), 0, s, (const int32_t*)g->col,
+              (const int32_t*)g->src, E2, NWp, K, npad, (const uint64_t*)bits.get(), (const int32_t*)wpre.get(),
+              out->col, out->src);
+    if (total > 0)
+        TC_LAUNCH("nz_relabel", k_nz_relabel, dim3(grid_for(total, 256)), dim3(256), 0, s, total,
+                  (const int4*)nzt.get(), out->col, out->src);
     TC_LAUNCH("comp_edges", k_comp_edges, dim3(ceil_div(K, 256)), dim3(256), 0, s, K, (const int32_t*)off,
               (const int32_t*)out->row_ptr, mk);
+}
+
+void comp_from_offsets(int64_t n, int32_t K, const int32_t* off, int32_t* comp, hipStream_t s) {
+    if (n > 0 && K > 0)
+        TC_LAUNCH("comp_from_off", k_comp_from_off, dim3(grid_for(n, 256)), dim3(256), 0, s, n, K, off, comp);
 }
 
 void sample_union_components(const tc_graph_s* gU, int32_t K, const int32_t* comp, const int32_t* off,

@@ -136,6 +136,45 @@ void check_request(const tc_request* r) {
     if (2 * r->num_pairs > 0x7fffffffLL) fail(TC_ERR_OVERFLOW, "2*num_pairs exceeds 2^31-1 (int32 CSR)");
 }
 
+// Requests a fused group may hold, and its pairs as a multiple of the fusion threshold.
+constexpr int kFuseMaxJobs = 64;
+constexpr int64_t kFusePairsFactor = 8;
+
+bool fusible(const tc_request& r, int32_t fuse_max_pairs) {
+    return fuse_max_pairs > 0 && !r.graph && r.num_pairs <= fuse_max_pairs;
+}
+
+int64_t pad_vertices(int64_t n) { return (n + kUnionAlign - 1) / kUnionAlign * kUnionAlign; }
+
+// Arena bytes of a fused group: an upper bound of the sum of the sizes of
+// every allocation its union build, union sample and union count make.
+int64_t group_bytes(const std::vector<const tc_request*>& rs) {
+    auto rb = region_bytes;
+    const CountConfig cfg;
+    const int64_t K = (int64_t)rs.size();
+    int64_t P = 0, nU = 0, hsum = 0, ubytes = 0, ntiles = 0;
+    int32_t maxd = 0;
+    for (const tc_request* r : rs) {
+        P += r->num_pairs;
+        nU += pad_vertices(r->n);
+        maxd = std::max<int32_t>(maxd, (int32_t)std::max<int64_t>(0, std::min<int64_t>(r->n - 1, 2 * r->num_pairs)));
+        const double hb = 2.0 * std::sqrt((double)r->num_pairs) + 2.0;  // h < 2 m'^(1/2) at c = 1, m' <= pairs
+        const int64_t h = std::min<int64_t>(r->n, (int64_t)hb);
+        if (h >= 3) {
+            const int64_t p = (h + 127) / 128 * 128;
+            hsum += h;
+            ubytes += p * p;
+            ntiles += (p / 128) * (p / 128 + 1) / 2;
+        }
+    }
+    const int64_t E2 = 2 * P, NW = (E2 + 63) / 64;
+    int64_t b = 2 * rb(4 * P) + build_csr_bytes(nU, P) + rb(4);          // staging, build, max degree
+    b += rb(4 * nU) + rb(4 * (K + 1)) + 3 * rb(8 * K) + rb(8 * kCountSlots * K);  // comp, off, salts, thrs, m', results
+    b += rb(4 * (nU + 1)) + rb(4 * nU) + rb(8 * NW) + rb(4 * (NW + 1)) + scan_scratch_bytes(NW) + 2 * rb(4 * E2);
+    b += count_union_bytes(nU, P, maxd, (int32_t)K, hsum, ubytes, ntiles, cfg);
+    return b;
+}
+
 int64_t request_bytes(const tc_request* r) {
     const int sampled = r->p < 1.0 ? 1 : 0;
     const CountConfig cfg;  // requests run with the library defaults
@@ -167,8 +206,10 @@ struct tc_server_s {
     std::vector<hipStream_t> streams;
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+    int64_t ranges_size() const { return cfg.budget_bytes / 256 * 256; }
     void lane_main(int lane);
     void run(int lane, const tc::Job& job, char* base, tc_result* res);
+    void run_fused(int lane, const std::vector<tc::Job>& jobs, char* base, int64_t bytes, std::vector<tc_result>& res);
 };
 
 namespace {
@@ -221,6 +262,124 @@ void tc_server_s::run(int lane, const tc::Job& job, char* base, tc_result* res) 
     res->spilled_bytes = region.spilled;
 }
 
+// A fused group: the requests' pairs, ids shifted to disjoint ranges padded
+// to kUnionAlign, built as one graph; component k sampled with request k's
+// (p, seed) and counted into its own result slots by one pass of the count.
+// A request with an id outside [0, n) fails alone and joins no union.
+void tc_server_s::run_fused(int lane, const std::vector<tc::Job>& jobs, char* base, int64_t bytes,
+                            std::vector<tc_result>& res) {
+    using namespace tc;
+    hipStream_t s = streams[(size_t)lane];
+    Reservation region(base, bytes);
+    AllocRegion* prev = set_thread_region(&region);
+    std::vector<int> members;  // jobs in the union, in order
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        const tc_request& r = jobs[i].req;
+        bool ok = true;
+        for (int64_t e = 0; e < r.num_pairs && ok; ++e)
+            ok = r.src[e] >= 0 && r.src[e] < r.n && r.dst[e] >= 0 && r.dst[e] < r.n;
+        if (ok) {
+            members.push_back((int)i);
+        } else {
+            res[i].status = TC_ERR_INVALID;
+            set_msg(&res[i], "vertex id outside [0, n)");
+        }
+    }
+    const int32_t K = (int32_t)members.size();
+    try {
+        if (K > 0) {
+            std::vector<int32_t> off((size_t)K + 1, 0);
+            std::vector<uint64_t> salts((size_t)K), thrs((size_t)K);
+            int64_t P = 0;
+            for (int32_t k = 0; k < K; ++k) {
+                const tc_request& r = jobs[(size_t)members[(size_t)k]].req;
+                off[(size_t)k + 1] = (int32_t)(off[(size_t)k] + pad_vertices(r.n));
+                salts[(size_t)k] = sample_salt(r.seed);
+                thrs[(size_t)k] = keep_threshold(r.p);
+                P += r.num_pairs;
+            }
+            const int64_t nU = off[(size_t)K];
+            if (nU > 0x7fffffffLL || 2 * P > 0x7fffffffLL) fail(TC_ERR_OVERFLOW, "fused group exceeds int32 ids");
+            std::vector<int32_t> hs((size_t)P), hd((size_t)P);
+            int64_t at = 0;
+            for (int32_t k = 0; k < K; ++k) {
+                const tc_request& r = jobs[(size_t)members[(size_t)k]].req;
+                const int32_t o = off[(size_t)k];
+                for (int64_t e = 0; e < r.num_pairs; ++e) {
+                    hs[(size_t)at] = r.src[e] + o;
+                    hd[(size_t)at] = r.dst[e] + o;
+                    ++at;
+                }
+            }
+            const CountConfig cfg;
+            tc_graph_s* gu = graph_from_pairs(nU, P, hs.data(), hd.data(), 0, s);
+            tc_graph_s* gs = new tc_graph_s();
+            try {
+                DevBuf<int32_t> comp(nU, s), offd((size_t)K + 1, s);
+                DevBuf<uint64_t> saltd(K, s), thrd(K, s);
+                DevBuf<int64_t> mk(K, s), accs((size_t)K * kCountSlots, s);
+                check_hip(hipMemcpyAsync(offd.get(), off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, s),
+                          "offsets");
+                check_hip(hipMemcpyAsync(saltd.get(), salts.data(), sizeof(uint64_t) * (size_t)K, hipMemcpyHostToDevice,
+                                         s), "salts");
+                check_hip(hipMemcpyAsync(thrd.get(), thrs.data(), sizeof(uint64_t) * (size_t)K, hipMemcpyHostToDevice, s),
+                          "thresholds");
+                comp_from_offsets(nU, K, offd.get(), comp.get(), s);
+                sample_union_components(gu, K, comp.get(), offd.get(), saltd.get(), thrd.get(), s, gs, mk.get());
+                CountUnion un;
+                un.K = K;
+                un.comp = comp.get();
+                un.off = offd.get();
+                un.mk = mk.get();
+                count_union(gs, un, cfg, s, accs.get());
+                std::vector<int64_t> h((size_t)K * kCountSlots);
+                check_hip(hipMemcpyAsync(h.data(), accs.get(), sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, s),
+                          "results");
+                check_hip(hipStreamSynchronize(s), "sync");
+                for (int32_t k = 0; k < K; ++k) {
+                    tc_result& x = res[(size_t)members[(size_t)k]];
+                    counts_from_slots(h.data() + (size_t)k * kCountSlots, &x.counts);
+                    x.estimate = rescale(x.counts.triangles, jobs[(size_t)members[(size_t)k]].req.p);
+                    x.status = TC_OK;
+                }
+            } catch (...) {
+                (void)hipStreamSynchronize(s);
+                graph_release(gs);
+                graph_release(gu);
+                throw;
+            }
+            graph_release(gs);
+            graph_release(gu);
+        }
+    } catch (const Error& e) {
+        for (int m : members) {
+            res[(size_t)m].status = e.status;
+            set_msg(&res[(size_t)m], e.msg);
+        }
+    } catch (const std::exception& e) {
+        for (int m : members) {
+            res[(size_t)m].status = TC_ERR_DEVICE;
+            set_msg(&res[(size_t)m], e.what());
+        }
+    } catch (...) {
+        for (int m : members) {
+            res[(size_t)m].status = TC_ERR_DEVICE;
+            set_msg(&res[(size_t)m], "unknown error");
+        }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess)
+        for (int m : members)
+            if (res[(size_t)m].status == TC_OK) {
+                res[(size_t)m].status = TC_ERR_DEVICE;
+                set_msg(&res[(size_t)m], "stream synchronisation failed");
+            }
+    set_thread_region(prev);
+    for (auto& x : res) {
+        x.peak_bytes = region.high();
+        x.spilled_bytes = region.spilled;
+    }
+}
+
 void tc_server_s::lane_main(int lane) {
     if (device >= 0) (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
@@ -235,6 +394,54 @@ void tc_server_s::lane_main(int lane) {
         if (head.release_s > t) {
             cv_work.wait_for(lk, std::chrono::duration<double>(head.release_s - t));
             continue;
+        }
+        // a small request takes the released small requests right behind it
+        if (tc::fusible(head.req, cfg.fuse_max_pairs)) {
+            std::vector<const tc_request*> grp{&head.req};
+            int64_t pairs = head.req.num_pairs;
+            for (size_t j = 1; j < queue.size() && grp.size() < (size_t)tc::kFuseMaxJobs; ++j) {
+                const tc::Job& q = queue[j];
+                if (!tc::fusible(q.req, cfg.fuse_max_pairs) || q.release_s > t ||
+                    pairs + q.req.num_pairs > tc::kFusePairsFactor * cfg.fuse_max_pairs)
+                    break;
+                grp.push_back(&q.req);
+                pairs += q.req.num_pairs;
+            }
+            if (grp.size() >= 2) {
+                const int64_t gbytes = tc::group_bytes(grp);
+                int64_t goff = 0;
+                if (gbytes <= ranges_size() && ranges.take(gbytes, &goff)) {
+                    std::vector<tc::Job> jobs(queue.begin(), queue.begin() + (long)grp.size());
+                    for (size_t j = 0; j < grp.size(); ++j) queue.pop_front();
+                    running += (int64_t)jobs.size();
+                    std::vector<tc_result> res(jobs.size());
+                    const double st = now();
+                    for (size_t j = 0; j < jobs.size(); ++j) {
+                        res[j].id = jobs[j].req.id;
+                        res[j].lane = lane;
+                        res[j].arrival_s = jobs[j].release_s;
+                        res[j].reserved_bytes = gbytes;
+                        res[j].start_s = st;
+                    }
+                    cv_work.notify_all();
+                    lk.unlock();
+                    run_fused(lane, jobs, arena + goff, gbytes, res);
+                    const double dn = now();
+                    lk.lock();
+                    ranges.give(goff, gbytes);
+                    running -= (int64_t)jobs.size();
+                    completed += (int64_t)jobs.size();
+                    for (auto& x : res) {
+                        x.done_s = dn;
+                        spilled += x.spilled_bytes;
+                        done.push_back(x);
+                    }
+                    cv_done.notify_all();
+                    cv_work.notify_all();
+                    continue;
+                }
+                // the group does not fit now: the head goes alone
+            }
         }
         int64_t off = 0;
         if (!ranges.take(head.bytes, &off)) {
@@ -304,6 +511,7 @@ tc_status tc_server_create(const tc_server_config* cfg, tc_server* out) {
         if (!cfg || !out) fail(TC_ERR_INVALID, "config or output is NULL");
         if (cfg->budget_bytes < 0) fail(TC_ERR_INVALID, "budget_bytes must be >= 0");
         if (cfg->lanes < 1 || cfg->lanes > 16) fail(TC_ERR_INVALID, "lanes must be in [1, 16]");
+        if (cfg->fuse_max_pairs < 0) fail(TC_ERR_INVALID, "fuse_max_pairs must be >= 0");
         tc_server_s* sv = new tc_server_s();
         sv->cfg = *cfg;
         try {

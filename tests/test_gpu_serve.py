@@ -161,3 +161,67 @@ def test_serving_workload_largest_request(gpu):
              % (p, x["counts"]["triangles"], 1e3 * (x["done_s"] - x["arrival_s"]), x["peak_bytes"] / 2**20,
                 x["reserved_bytes"] / 2**20))
     g.free()
+
+
+def _groups(res):
+    # requests that ran as one fused group share their admission and completion times
+    by = {}
+    for x in res:
+        by.setdefault((x["lane"], x["start_s"], x["done_s"]), []).append(x["id"])
+    return [g for g in by.values() if len(g) > 1]
+
+
+def test_fused_small_requests_equal_alone_and_oracle(gpu):
+    # small requests fused into one union build and count: every result equals
+    # the request run alone and the oracle's count, whatever it was fused with
+    tc = gpu
+    reqs = _mix(40, 6, 12, seed=19)
+    with tc.Server(1 << 30, lanes=2, fuse_max_pairs=1 << 16) as sv:
+        for r in reqs:
+            sv.submit(r["id"], r["p"], r["seed"], n=r["n"], src=r["src"], dst=r["dst"])
+        res = sv.drain()
+        st = sv.stats()
+    assert len(res) == len(reqs) and st["spilled_bytes"] == 0
+    groups = _groups(res)
+    _log("fused: %d groups, sizes %s" % (len(groups), sorted(len(g) for g in groups)))
+    assert groups, "no request was fused"
+    by_id = {x["id"]: x for x in res}
+    for r in reqs:
+        x = by_id[r["id"]]
+        assert x["status"] == 0, x["message"]
+        assert 0 < x["peak_bytes"] <= x["reserved_bytes"] and x["spilled_bytes"] == 0
+        counts, est = _alone(tc, r)
+        assert x["counts"] == counts, r["id"]
+        assert x["estimate"] == est
+        assert x["counts"]["triangles"] == _oracle_T(r), r["id"]
+
+
+def test_fused_group_with_a_bad_request(gpu):
+    tc = gpu
+    reqs = _mix(6, 6, 9, seed=23)
+    bad = dict(id=999, n=10, src=np.array([0, 1, 50], np.int32), dst=np.array([1, 2, 3], np.int32), p=0.5, seed=0)
+    with tc.Server(1 << 30, lanes=1, fuse_max_pairs=1 << 16) as sv:
+        for r in reqs[:3] + [bad] + reqs[3:]:
+            sv.submit(r["id"], r["p"], r["seed"], n=r["n"], src=r["src"], dst=r["dst"])
+        res = sv.drain()
+    by_id = {x["id"]: x for x in res}
+    assert by_id[999]["status"] == 1 and "outside" in by_id[999]["message"]
+    for r in reqs:
+        assert by_id[r["id"]]["status"] == 0
+        assert by_id[r["id"]]["counts"] == _alone(tc, r)[0]
+
+
+def test_fusion_leaves_large_requests_alone(gpu):
+    # requests above the threshold run alone; the small ones around them fuse
+    tc = gpu
+    reqs = _mix(16, 8, 14, seed=29)
+    with tc.Server(1 << 30, lanes=2, fuse_max_pairs=1 << 14) as sv:
+        for r in reqs:
+            sv.submit(r["id"], r["p"], r["seed"], n=r["n"], src=r["src"], dst=r["dst"])
+        res = sv.drain()
+    by_id = {x["id"]: x for x in res}
+    for g in _groups(res):
+        assert all(len(by_id[i]["counts"]) and next(r for r in reqs if r["id"] == i)["src"].size <= 1 << 14 for i in g)
+    for r in reqs:
+        assert by_id[r["id"]]["status"] == 0
+        assert by_id[r["id"]]["counts"] == _alone(tc, r)[0]
