@@ -26,7 +26,7 @@ def build():
     src = os.path.join(_HERE, "tc_oracle.c")
     tmp = _SO + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
-                           "-fno-fast-math", "-o", tmp, src])
+                           "-fno-fast-math", "-o", tmp, src, "-lm"])
     os.replace(tmp, _SO)
 
 
@@ -81,6 +81,14 @@ def _load():
     L.or_triple_sample.restype = ctypes.c_int
     L.or_triple_estimate.argtypes = [i64, i64, i64, dbl]
     L.or_triple_estimate.restype = dbl
+    L.or_stream_draws.argtypes = [i64, i64, dbl]
+    L.or_stream_draws.restype = i64
+    L.or_stream_closed_all.argtypes = [i64, P(i64), P(i32), P(ctypes.c_uint8)]
+    L.or_stream_closed_all.restype = i64
+    L.or_stream_estimate.argtypes = [i64, P(i64), P(i32), dbl, i64, u64, P(i64), P(ctypes.c_uint8)]
+    L.or_stream_estimate.restype = ctypes.c_int
+    L.or_stream_value.argtypes = [i64, i64, i64]
+    L.or_stream_value.restype = dbl
     _lib = L
     return L
 
@@ -286,3 +294,33 @@ def dense_adjacency(g):
     for u in range(n):
         A[u, col[rp[u]:rp[u + 1]]] = 1
     return A
+
+
+def stream_draws(n, m, d):
+    """Pass 1 of the semi-streaming variant: ceil(d m^(1/2) ln n) edge draws."""
+    return int(_load().or_stream_draws(n, m, float(d)))
+
+
+def stream_closed_all(g, heavy):
+    """Closed elements among all of the semi-streaming triple set U for the
+    heavy set given by the flags ``heavy`` (every element counted once)."""
+    n, rp, col = g
+    h = np.ascontiguousarray(heavy, dtype=np.uint8)
+    return int(_load().or_stream_closed_all(n, _i64(rp), _i32(col), _p(h, ctypes.c_uint8)))
+
+
+def stream_estimate(g, d, s, seed):
+    """Semi-streaming three-pass estimate (section 5.2): dict(draws1,
+    candidates, heavy, light_size, size, queries, closed, m, estimate) and
+    the flags of the heavy set."""
+    n, rp, col = g
+    out = np.zeros(8, np.int64)
+    heavy = np.zeros(max(n, 1), np.uint8)
+    rc = _load().or_stream_estimate(n, _i64(rp), _i32(col), float(d), int(s), seed & (2 ** 64 - 1), _i64(out),
+                                    _p(heavy, ctypes.c_uint8))
+    if rc:
+        raise MemoryError("oracle stream")
+    keys = ("draws1", "candidates", "heavy", "light_size", "size", "queries", "closed", "m")
+    r = {k: int(v) for k, v in zip(keys, out)}
+    r["estimate"] = float(_load().or_stream_value(r["size"], r["closed"], int(s))) if s > 0 else 0.0
+    return r, heavy[:n].astype(bool)

@@ -26,6 +26,7 @@
  * that does not re-derive it from itself (closed forms, brute force, dense
  * linear algebra, published SplitMix64 output vectors, statistical laws).
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -503,4 +504,172 @@ double or_triple_estimate(int64_t size, int64_t wsum, int64_t s, double p) {
     volatile double p2 = p * p;
     volatile double p3 = p2 * p;
     return t / p3;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Semi-streaming variant (section 5.2): three passes over the edge stream,   */
+/* the adjacency lists given in order.                                        */
+/*                                                                            */
+/* Pass 1: s1 = ceil(d m^(1/2) ln n) edges drawn uniformly with replacement   */
+/* (the Lemma of section 5.2: every vertex of degree above m^(1/2) is then an */
+/* endpoint of a drawn edge with probability at least 1 - n^(1-d)); their    */
+/* endpoints are the heavy candidates C, and one more pass over the edges     */
+/* (their degrees) keeps H = {x in C : deg(x)^2 > m}.                         */
+/* Pass 2: the triples to check are U = L followed by X:                      */
+/*   L: for every vertex u not in H (ascending), its wedges (N(u)[a], u,      */
+/*      N(u)[b]), a < b positions in colex order; closed iff the ends are     */
+/*      adjacent;                                                             */
+/*   X: for every h in H (ascending) and every edge e = {v, w} (v < w, in     */
+/*      (v, w) order), the pair (h; e); closed iff h is not in e and adjacent */
+/*      to both ends.                                                         */
+/* Every triangle has exactly three closed elements in U, one per vertex (a   */
+/* wedge at a vertex outside H, a pair at a vertex of H), so with s draws     */
+/* with replacement, t = |U| closed / (3 s) is unbiased.                      */
+/* Pass 3: the closing edges the draws ask for are looked up in one pass over */
+/* the edges; here the lookup is the definition itself (adjacency).          */
+/*                                                                            */
+/* Draw i of pass 1 is upper edge floor(h m / 2^64) (h = mix64(mix64(i) ^     */
+/* mix64(seed ^ "TC_STRM1"))), draw j of pass 2 is element                    */
+/* floor(h' |U| / 2^64) of U (h' = mix64(mix64(j) ^ mix64(seed ^             */
+/* "TC_STRM2"))).                                                             */
+/* ------------------------------------------------------------------------- */
+
+static int64_t hi_mul(uint64_t h, uint64_t size) { return (int64_t)(((unsigned __int128)h * size) >> 64); }
+
+int64_t or_stream_draws(int64_t n, int64_t m, double d) {
+    if (n < 2 || m < 1) return 0;
+    return (int64_t)ceil(d * sqrt((double)m) * log((double)n));
+}
+
+/* (u, v) of upper edge r (0 <= r < m): up[u] = number of neighbours of u
+   above u, upre its exclusive prefix */
+static void upper_edge(int64_t n, const int64_t* row_ptr, const int32_t* col, const int64_t* upre, int64_t r,
+                       int32_t* u, int32_t* v) {
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (upre[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t deg = row_ptr[lo + 1] - row_ptr[lo];
+    const int64_t up = upre[lo + 1] - upre[lo];
+    *u = (int32_t)lo;
+    *v = col[row_ptr[lo] + (deg - up) + (r - upre[lo])];
+}
+
+/* closed elements among all of U for a given heavy set (flags[x] != 0):
+   sums over every element, for the pins */
+int64_t or_stream_closed_all(int64_t n, const int64_t* row_ptr, const int32_t* col, const uint8_t* heavy) {
+    int64_t closed = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        if (heavy[u]) continue;
+        for (int64_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a)
+            for (int64_t b = a + 1; b < row_ptr[u + 1]; ++b) closed += adjacent(row_ptr, col, col[a], col[b]);
+    }
+    for (int64_t h = 0; h < n; ++h) {
+        if (!heavy[h]) continue;
+        for (int64_t v = 0; v < n; ++v)
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                const int32_t w = col[e];
+                if (w <= v || h == v || h == w) continue;
+                closed += adjacent(row_ptr, col, (int32_t)h, (int32_t)v) && adjacent(row_ptr, col, (int32_t)h, w);
+            }
+    }
+    return closed;
+}
+
+/*
+ * The semi-streaming estimate with candidate multiplier d, s draws of pass 2
+ * and the given seed.  out[0] = s1, out[1] = |C|, out[2] = |H|, out[3] = |L|,
+ * out[4] = |U|, out[5] = edge queries of pass 3 (one per wedge, two per pair
+ * whose vertex is not in its edge), out[6] = closed draws, out[7] = m.
+ * heavy (n bytes, may be NULL) receives the flags of H.  Returns 0, or 2 on
+ * allocation failure.
+ */
+int or_stream_estimate(int64_t n, const int64_t* row_ptr, const int32_t* col, double d, int64_t s, uint64_t seed,
+                       int64_t* out, uint8_t* heavy) {
+    const int64_t m = row_ptr[n] / 2;
+    int64_t* upre = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t* lpre = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    uint8_t* cand = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+    int32_t* hlist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!upre || !lpre || !cand || !hlist) {
+        free(upre); free(lpre); free(cand); free(hlist);
+        return 2;
+    }
+    upre[0] = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        int64_t up = 0;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) up += col[e] > u;
+        upre[u + 1] = upre[u] + up;
+    }
+    /* pass 1: candidates, then H */
+    const int64_t s1 = or_stream_draws(n, m, d);
+    const uint64_t salt1 = or_mix64(seed ^ 0x54435F5354524D31ULL); /* "TC_STRM1" */
+    for (int64_t i = 0; i < s1; ++i) {
+        int32_t u, v;
+        upper_edge(n, row_ptr, col, upre, hi_mul(or_mix64(or_mix64((uint64_t)i) ^ salt1), (uint64_t)m), &u, &v);
+        cand[u] = 1;
+        cand[v] = 1;
+    }
+    int64_t nc = 0, nh = 0;
+    for (int64_t x = 0; x < n; ++x) {
+        nc += cand[x];
+        const int64_t dx = row_ptr[x + 1] - row_ptr[x];
+        const int hv = cand[x] && or_is_heavy(dx, m, 1, 1);
+        if (heavy) heavy[x] = (uint8_t)hv;
+        if (hv) hlist[nh++] = (int32_t)x;
+        cand[x] = (uint8_t)hv; /* from here on: the flags of H */
+    }
+    /* pass 2: U = L (wedges at vertices outside H) followed by X = H x E */
+    lpre[0] = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        const int64_t du = row_ptr[u + 1] - row_ptr[u];
+        lpre[u + 1] = lpre[u] + (cand[u] ? 0 : du * (du - 1) / 2);
+    }
+    const int64_t L = lpre[n], size = L + nh * m;
+    const uint64_t salt2 = or_mix64(seed ^ 0x54435F5354524D32ULL); /* "TC_STRM2" */
+    int64_t queries = 0, closed = 0;
+    for (int64_t j = 0; size > 0 && j < s; ++j) {
+        const int64_t r = hi_mul(or_mix64(or_mix64((uint64_t)j) ^ salt2), (uint64_t)size);
+        if (r < L) {
+            int64_t lo = 0, hi = n - 1; /* the vertex u with lpre[u] <= r < lpre[u+1] */
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo + 1) / 2;
+                if (lpre[mid] <= r) lo = mid;
+                else hi = mid - 1;
+            }
+            const int64_t k = r - lpre[lo];
+            int64_t b = 1; /* the largest b with b (b - 1) / 2 <= k */
+            while ((b + 1) * b / 2 <= k) ++b;
+            const int64_t a = k - b * (b - 1) / 2;
+            queries += 1;
+            closed += adjacent(row_ptr, col, col[row_ptr[lo] + a], col[row_ptr[lo] + b]);
+        } else {
+            const int64_t q = r - L;
+            const int32_t h = hlist[q / m];
+            int32_t v, w;
+            upper_edge(n, row_ptr, col, upre, q % m, &v, &w);
+            if (h == v || h == w) continue;
+            queries += 2;
+            closed += adjacent(row_ptr, col, h, v) && adjacent(row_ptr, col, h, w);
+        }
+    }
+    out[0] = s1;
+    out[1] = nc;
+    out[2] = nh;
+    out[3] = L;
+    out[4] = size;
+    out[5] = queries;
+    out[6] = closed;
+    out[7] = m;
+    free(upre); free(lpre); free(cand); free(hlist);
+    return 0;
+}
+
+/* |U| closed / (3 s) */
+double or_stream_value(int64_t size, int64_t closed, int64_t s) {
+    volatile double num = (double)size * (double)closed;
+    volatile double den = 3.0 * (double)s;
+    return num / den;
 }
