@@ -440,6 +440,63 @@ def rp_workload(args):
           flush=True)
 
 
+def stream_workload(args):
+    """Semi-streaming three-pass estimate (section 5.2) on R-MAT scale 22 with
+    d = 1 and 2^24 pass-2 draws: time per call, draws per second, every
+    pass's kernel time, the estimate against the exact count, and parity of
+    the seed-0 and seed-1 results with the oracle's stored values.  Roofline
+    of pass 3 (the edge pass): 8 B per CSR entry read (its row and column)
+    and 8 B per upper edge looked up in the query table."""
+    import torch
+    import synth
+    import paper_1011_0468_amd as tc
+    n, s, d = synth.workload("rmat22")
+    g = tc.tc_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    del s, d
+    info = g.info()
+    S, dd = 1 << 24, 1.0
+    golden = _load_golden("stream22.json")
+    parity = None
+    if golden:
+        parity = all(tc.tc_stream_estimate(g, dd, S, seed=r["seed"]) ==
+                     {k: r[k] for k in ("draws1", "candidates", "heavy", "light_size", "size", "queries", "closed",
+                                        "m", "estimate")} for r in golden["runs"])
+    for _ in range(args.warmup):
+        tc.tc_stream_estimate(g, dd, S, seed=args.seed)
+    tc.profile.select([])
+    tc.profile.reset()
+    tc.profile.enable(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        r = tc.tc_stream_estimate(g, dd, S, seed=args.seed)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    tc.profile.enable(False)
+    kern = {}
+    for name in ("stream_up", "stream_index", "stream_pass1", "stream_classify", "stream_hlist", "stream_pass2",
+                 "stream_pass3", "stream_count"):
+        tot, cnt = tc.profile.read(name)
+        if cnt:
+            kern[name] = {"ms_per_call": round(tot / args.steps, 4), "launches_per_call": cnt // args.steps}
+    m = info["m"]
+    p3_bytes = 8 * 2 * m + 8 * m
+    p3_ms = kern.get("stream_pass3", {}).get("ms_per_call", 0.0)
+    gbs = p3_bytes / (p3_ms / 1e3) / 1e9 if p3_ms else 0.0
+    exact = golden["exact"] if golden else None
+    print(json.dumps({"metric": "semi-streaming estimate, pass-2 draws/sec at R-MAT s22 (d = 1, 2^24 draws)",
+                      "value": round(S / (ms / 1e3), 1), "unit": "draws/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_call": round(ms, 4), "higher_is_better": True,
+                      "dtype": "int64", "data": "synthetic", "result": r, "exact": exact,
+                      "rel_error": (r["estimate"] / exact - 1.0) if exact else None, "parity_vs_oracle": parity,
+                      "kernels": kern,
+                      "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "stream_pass3",
+                                   "model_bytes_per_launch": p3_bytes},
+                      "config": {"workload": "stream_rmat22", "n": info["n"], "m": m, "d": dd, "num_samples": S,
+                                 "seed": args.seed}}), flush=True)
+
+
 def copy_probe(mib):
     """A plain device copy of known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -499,6 +556,9 @@ def main():
         return
     if args.workload == "heavy":
         heavy_stress(args)
+        return
+    if args.workload == "stream":
+        stream_workload(args)
         return
     if args.workload == "rp":
         rp_workload(args)
@@ -698,6 +758,14 @@ def phase_breakdown(tc, step, res, info, csr_ms, pairs):
     out["note"] = ("kernel time from HIP events around every launch of one untimed step; the csr_build time is "
                    "the wall time of tc_build_csr")
     return out, ms
+
+
+def _load_golden(name):
+    """A stored oracle result under tests/golden (None if absent)."""
+    try:
+        return json.load(open(os.path.join(ROOT, "tests", "golden", name)))
+    except (OSError, ValueError):
+        return None
 
 
 def golden_parity(workload, seed, res, tunings):

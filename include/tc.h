@@ -8,7 +8,8 @@
  * with probability p (section 3.1), split the vertices at m^(1/2) into light
  * and heavy sets (section 3.2), count exactly on the sparsified graph and
  * rescale by 1/p^3 (section 3.1; the "Sparsified + Exact" columns of Table 2),
- * plus the random-projection trace estimator of section 5.1.
+ * plus the random-projection trace estimator of section 5.1 and the
+ * three-pass semi-streaming variant of section 5.2.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -206,6 +207,44 @@ typedef struct {
 
 tc_status tc_triple_estimate(tc_graph g, double p, uint64_t sample_seed, int32_t hybrid, int64_t num_samples,
                              uint64_t triple_seed, void* stream, tc_triple_result* out);
+
+/* Semi-streaming estimate (section 5.2 and its Lemma): three passes over the
+   edges of g, with g's adjacency lists in order (the layout of tc_graph).
+   Edges are numbered as upper entries: edge r is the (r - upre[u])-th
+   neighbour above u of the vertex u with upre[u] <= r < upre[u+1], where
+   upre is the exclusive prefix over u of the neighbours above u.
+   Pass 1 draws s1 = ceil(d m^(1/2) ln n) edges with replacement (draw i is
+   edge floor(h m / 2^64), h = mix64(mix64(i) ^ mix64(seed ^
+   0x54435F5354524D31))); their endpoints are the candidates, and the
+   candidates with deg^2 > m form H.  Pass 2 draws num_samples elements with
+   replacement (draw j is element floor(h' |U| / 2^64), h' = mix64(mix64(j) ^
+   mix64(seed ^ 0x54435F5354524D32))) of U = L followed by X: L holds, for
+   every vertex u outside H (ascending), its pairs of neighbour positions
+   a < b in colex order, closed iff N(u)[a] and N(u)[b] are adjacent; X holds,
+   for every h of H (ascending) and every edge e = (v, w) in edge order, the
+   pair (h; e), closed iff h is not in e and h is adjacent to v and w.  Pass 3
+   looks up the closing edges the draws ask for (one for a wedge, two for a
+   pair whose vertex is not in its edge, none otherwise).  estimate =
+   ((double)|U| * (double)closed) / (3.0 * (double)num_samples), 0 when
+   num_samples = 0; every field is 0 except m, draws1 when n < 2 or m = 0.
+   d > 0 and finite and num_samples >= 0, else TC_ERR_INVALID;
+   TC_ERR_OVERFLOW if num_samples > 2^28 or s1 > 2^40.  The device memory it
+   takes (through the allocator) is at most 72 num_samples + 49 (n + 1) bytes
+   plus 17 KiB and the scans' scratch. */
+typedef struct {
+    int64_t draws1;      /* s1, the edge draws of pass 1 */
+    int64_t candidates;  /* distinct endpoints of the pass-1 draws */
+    int64_t heavy;       /* |H| */
+    int64_t light_size;  /* |L| */
+    int64_t size;        /* |U| = |L| + |H| m */
+    int64_t queries;     /* closing-edge lookups of pass 3 */
+    int64_t closed;      /* closed draws */
+    int64_t m;           /* edges of g */
+    double estimate;     /* of the triangle count of g */
+} tc_stream_result;
+
+tc_status tc_stream_estimate(tc_graph g, double d, int64_t num_samples, uint64_t seed, void* stream,
+                             tc_stream_result* out);
 
 /* Random-projection estimator (section 5.1) with Rademacher vectors: for
    l < k, x_l[i] = +1 if bit (l & 63) of

@@ -15,10 +15,10 @@ import ctypes
 import numpy as np
 
 from . import _native
-from ._native import (TcCounts, TcError, TcParams, TcRequest, TcResult, TcServerConfig, TcServerInfo, TcStage, TcTripleResult, TcTuning,
+from ._native import (TcCounts, TcError, TcParams, TcRequest, TcResult, TcServerConfig, TcServerInfo, TcStage, TcStreamResult, TcTripleResult, TcTuning,
                       check)
 
-__all__ = ["Graph", "tc_build_csr", "tc_sample", "tc_count_exact", "tc_estimate", "tc_estimate_adaptive", "tc_triple_estimate", "tc_rp_trace",
+__all__ = ["Graph", "tc_build_csr", "tc_sample", "tc_count_exact", "tc_estimate", "tc_estimate_adaptive", "tc_triple_estimate", "tc_stream_estimate", "tc_rp_trace",
            "tc_graph_info", "tc_graph_read", "tc_tune_set", "tc_tune_get", "tc_autotune", "profile", "TcError",
            "Server", "tc_request_bytes"]
 
@@ -167,6 +167,15 @@ def tc_triple_estimate(g, p, num_samples, hybrid=False, sample_seed=0, triple_se
     check(_native.load().tc_triple_estimate(g.handle, float(p), int(sample_seed) & (2 ** 64 - 1), 1 if hybrid else 0,
                                             int(num_samples), int(triple_seed) & (2 ** 64 - 1), _stream_ptr(stream),
                                             ctypes.byref(r)))
+    return r.as_dict()
+
+
+def tc_stream_estimate(g, d, num_samples, seed=0, stream=None):
+    """Semi-streaming three-pass estimate (section 5.2): dict(draws1,
+    candidates, heavy, light_size, size, queries, closed, m, estimate)."""
+    r = TcStreamResult()
+    check(_native.load().tc_stream_estimate(g.handle, float(d), int(num_samples), int(seed) & (2 ** 64 - 1),
+                                            _stream_ptr(stream), ctypes.byref(r)))
     return r.as_dict()
 
 

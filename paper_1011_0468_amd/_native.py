@@ -51,6 +51,15 @@ class TcTripleResult(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class TcStreamResult(ctypes.Structure):
+    _fields_ = [("draws1", ctypes.c_int64), ("candidates", ctypes.c_int64), ("heavy", ctypes.c_int64),
+                ("light_size", ctypes.c_int64), ("size", ctypes.c_int64), ("queries", ctypes.c_int64),
+                ("closed", ctypes.c_int64), ("m", ctypes.c_int64), ("estimate", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class TcServerConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("lanes", ctypes.c_int32), ("fuse_max_pairs", ctypes.c_int32)]
 
@@ -94,7 +103,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 
 # every symbol declared in include/tc.h
 EXPORTS = ["tc_set_allocator", "tc_build_csr", "tc_graph_info", "tc_graph_csr", "tc_graph_read", "tc_sample",
-           "tc_count_exact", "tc_estimate", "tc_estimate_noalloc", "tc_estimate_adaptive", "tc_triple_estimate", "tc_rp_trace", "tc_tune_set", "tc_tune_get", "tc_autotune",
+           "tc_count_exact", "tc_estimate", "tc_estimate_noalloc", "tc_estimate_adaptive", "tc_triple_estimate", "tc_stream_estimate", "tc_rp_trace", "tc_tune_set", "tc_tune_get", "tc_autotune",
            "tc_graph_free", "tc_last_error",
            "tc_request_bytes", "tc_server_create", "tc_server_clock", "tc_server_submit", "tc_server_poll",
            "tc_server_stats", "tc_server_destroy",
@@ -125,6 +134,7 @@ def load():
         "tc_estimate_noalloc": [vp, dbl, u64, P(TcParams), vp, P(TcCounts), P(dbl)],
         "tc_estimate_adaptive": [vp, dbl, dbl, u64, i32, i32, i32, P(TcParams), vp, P(TcStage), P(i32), P(dbl)],
         "tc_triple_estimate": [vp, dbl, u64, i32, i64, u64, vp, P(TcTripleResult)],
+        "tc_stream_estimate": [vp, dbl, i64, u64, vp, P(TcStreamResult)],
         "tc_rp_trace": [vp, i32, u64, vp, P(i64), P(dbl)],
         "tc_tune_set": [vp, dbl, P(TcTuning)],
         "tc_tune_get": [vp, dbl, P(TcTuning)],

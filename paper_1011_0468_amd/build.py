@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtc.so")
-SOURCES = ["tc_api.hip", "tc_scan.hip", "tc_csr.hip", "tc_sample.hip", "tc_count.hip", "tc_rp.hip", "tc_tune.hip", "tc_serve.hip", "tc_triple.hip", "tc_noalloc.hip"]
+SOURCES = ["tc_api.hip", "tc_scan.hip", "tc_csr.hip", "tc_sample.hip", "tc_count.hip", "tc_rp.hip", "tc_tune.hip", "tc_serve.hip", "tc_triple.hip", "tc_noalloc.hip", "tc_stream.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

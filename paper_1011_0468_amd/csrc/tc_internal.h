@@ -155,6 +155,8 @@ int64_t scan_x4_scratch_bytes(int64_t N);
 // samples of num_samples samples of g's candidate triples.
 void triple_sample(const tc_graph_s* g, int hybrid, int64_t num_samples, uint64_t seed, hipStream_t s,
                    int64_t* size, int64_t* wsum, int64_t* closed);
+// exclusive scan of int64 values: out[0..N), out[N] = total (tc_triple.hip)
+void scan64(const int64_t* in, int64_t* out, int64_t N, hipStream_t s);
 void fill_i32(int32_t* p, int32_t v, int64_t N, hipStream_t s);
 void fill_i64(int64_t* p, int64_t v, int64_t N, hipStream_t s);
 void fill_u8(uint8_t* p, uint8_t v, int64_t N, hipStream_t s);

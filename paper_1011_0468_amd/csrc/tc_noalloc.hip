@@ -123,6 +123,7 @@ extern "C" tc_status tc_estimate_noalloc(tc_graph g, double p, uint64_t seed, co
         }
         *out = r;
         if (est) *est = rescale(r.triangles, p);
+        profile_collect();
         return TC_OK;
     } catch (const Error& e) {
         set_last_error(e.msg);

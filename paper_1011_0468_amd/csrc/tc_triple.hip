@@ -109,6 +109,8 @@ __global__ void k_scan64_fin(int64_t* out, int64_t N, const int64_t* __restrict_
     }
 }
 
+}  // namespace
+
 void scan64(const int64_t* in, int64_t* out, int64_t N, hipStream_t s) {
     const int64_t nb = N > 0 ? (N + kTile64 - 1) / kTile64 : 1;
     DevBuf<int64_t> bs(nb + 1, s);
@@ -117,6 +119,8 @@ void scan64(const int64_t* in, int64_t* out, int64_t N, hipStream_t s) {
     const int64_t g = std::min<int64_t>((N + 256) / 256, 65536);
     TC_LAUNCH("tri_scan", k_scan64_fin, dim3((unsigned)g), dim3(256), 0, s, out, N, (const int64_t*)bs.get(), nb);
 }
+
+namespace {
 
 // y in the sorted list of x
 __device__ __forceinline__ bool in_list(const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t x,

@@ -3,7 +3,7 @@
 Calls only the CPU oracle (oracle/) on inputs from the seeded generators
 (synth/); nothing here touches the device path.  Usage:
 
-    python tests/golden/make_golden.py rmat22 rmat22_splits cl20 rmat24 rmat24_count rmat22_top serve20
+    python tests/golden/make_golden.py rmat22 rmat22_splits cl20 rmat24 rmat24_count rmat22_top serve20 stream22
 
 Each section writes tests/golden/<name>.json.
 """
@@ -134,6 +134,20 @@ def rmat22_top():
         out[str(h)] = {"m": int(len(sub[2]) // 2), "triangles": int(oracle.count(sub))}
     return {"workload": "R-MAT scale 22 (generator seed 1), subgraph induced by the top-h degree vertices",
             "blocks": out}
+
+
+def stream22():
+    # the semi-streaming estimate (section 5.2) of the benchmark's stream
+    # workload: d = 1, 2^24 pass-2 draws, seeds 0 and 1
+    g = _graph("rmat22")
+    runs = []
+    for seed in (0, 1):
+        t = time.time()
+        r, heavy = oracle.stream_estimate(g, 1.0, 1 << 24, seed)
+        r.update(d=1.0, num_samples=1 << 24, seed=seed, oracle_seconds=round(time.time() - t, 2))
+        runs.append(r)
+    return {"workload": "R-MAT scale 22, edge factor 16, a/b/c = .57/.19/.19, generator seed 1", "runs": runs,
+            "exact": oracle.count(g)}
 
 
 if __name__ == "__main__":

@@ -98,6 +98,21 @@ def test_rmat22_every_operating_split_matches_golden(gpu, rmat22):
             assert got[k] == want[k], (p, a, b, k, got[k], want[k])
 
 
+def test_rmat22_stream_estimate_matches_golden(gpu, rmat22):
+    # the semi-streaming estimate (section 5.2) in the benchmark's
+    # configuration (d = 1, 2^24 pass-2 draws), every count and the estimate
+    # against the oracle's stored runs (tests/golden/stream22.json)
+    n, s, d, g = rmat22
+    gold = json.load(open(os.path.join(GOLDEN, "stream22.json")))
+    keys = ("draws1", "candidates", "heavy", "light_size", "size", "queries", "closed", "m", "estimate")
+    for want in gold["runs"]:
+        _log("rmat22: stream d=%g s=%d seed %d" % (want["d"], want["num_samples"], want["seed"]))
+        got = gpu.tc_stream_estimate(g, want["d"], want["num_samples"], seed=want["seed"])
+        assert got == {k: want[k] for k in keys}
+    # sampled relative error at 2^24 draws (about 40 closed draws per 10^6)
+    assert abs(got["estimate"] / gold["exact"] - 1.0) < 0.02
+
+
 def _timed(label, fn):
     import time
     import torch
