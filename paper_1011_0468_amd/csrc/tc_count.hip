@@ -935,7 +935,7 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D
     // every lane loads (lanes past b read colO[0], which exists whenever there
     // are positions) and nothing consumes the loaded values before the probe,
     // so these loads stay in flight across the caller's other work
-    const int32_t nxt = jlo + 1 < nl ? P[jlo + 1] : INT32_MAX;
+    const int32_t nxt = __builtin_amdgcn_readfirstlane(jlo + 1 < nl ? P[jlo + 1] : INT32_MAX);
     if (nxt >= g0 + 64 * U) {  // wave-uniform: one list covers the super-strip
         const int32_t d0 = D[jlo];
 #pragma unroll
@@ -990,9 +990,17 @@ template <int U, bool GLOBAL, bool SHORT>
 __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D, int nl, int32_t a, int32_t b,
                                               const int32_t* __restrict__ colO, const int32_t* tab, int lg,
                                               int32_t* mark, int lane) {
+    // a, b and nl are wave-uniform; saying so makes every exit of the
+    // pipelined loop below a scalar branch.  Otherwise the loop is compiled
+    // as a divergent one whose early exit reaches the loop head with the
+    // other register set's gathers still in flight, and the compiler then
+    // waits for all outstanding loads (vmcnt(0)) on every trip.
+    a = __builtin_amdgcn_readfirstlane(a);
+    b = __builtin_amdgcn_readfirstlane(b);
+    nl = __builtin_amdgcn_readfirstlane(nl);
     int32_t cnt = 0;
     if (a >= b) return 0;
-    int jlo = a == 0 ? 0 : find_list(P, nl, a);  // P[0] = 0 owns position 0
+    int jlo = a == 0 ? 0 : __builtin_amdgcn_readfirstlane(find_list(P, nl, a));  // P[0] = 0 owns position 0
     if (SHORT && b - a <= 64) {  // one strip
         int32_t x1[1];
         uint64_t v1[1];
@@ -1005,16 +1013,27 @@ __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D
         gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, x1, v1);
         return probe_many<U>(tab, lg, x1, v1);
     }
+    // super-strips i = 0 .. ns-1 start at a + i 64U.  The loop runs whole
+    // pairs and has one exit, where only set a is in flight; the last one or
+    // two super-strips follow it.
+    constexpr int32_t S = 64 * U;
+    const int32_t ns = (b - a + S - 1) / S;
     int32_t xa[U], xb[U];
     uint64_t va[U], vb[U];
     gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, xa, va);
-    for (int32_t g0 = a;; g0 += 2 * 64 * U) {
-        gather_strips<U, GLOBAL>(P, D, nl, g0 + 64 * U, b, colO, mark, lane, jlo, xb, vb);
+    int32_t i = 0;
+    for (; i + 2 < ns; i += 2) {
+        gather_strips<U, GLOBAL>(P, D, nl, a + (i + 1) * S, b, colO, mark, lane, jlo, xb, vb);
         cnt += probe_many<U>(tab, lg, xa, va);
-        if (g0 + 64 * U >= b) break;
-        gather_strips<U, GLOBAL>(P, D, nl, g0 + 2 * 64 * U, b, colO, mark, lane, jlo, xa, va);
+        gather_strips<U, GLOBAL>(P, D, nl, a + (i + 2) * S, b, colO, mark, lane, jlo, xa, va);
         cnt += probe_many<U>(tab, lg, xb, vb);
-        if (g0 + 2 * 64 * U >= b) break;
+    }
+    if (i + 1 < ns) {
+        gather_strips<U, GLOBAL>(P, D, nl, a + (i + 1) * S, b, colO, mark, lane, jlo, xb, vb);
+        cnt += probe_many<U>(tab, lg, xa, va);
+        cnt += probe_many<U>(tab, lg, xb, vb);
+    } else {
+        cnt += probe_many<U>(tab, lg, xa, va);
     }
     return cnt;
 }
@@ -1798,10 +1817,14 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
         degs.reset(n, s);
         cols.reset(E2, s);
         srcs.reset(E2, s);
-        sample_keep_bits(g, salt, thr, keep.get(), kpre.get(), s);
-        scan_exclusive_i32(kpre.get(), kpre.get(), NW, s);
-        positions_at_rows(g->row_ptr, n, E2, keep.get(), kpre.get(), rps.get(), degs.get(), s);
-        compact_kept(g->col, g->src, E2, keep.get(), kpre.get(), cols.get(), srcs.get(), s);
+        {
+            // staging freed before any later allocation (last in, first out)
+            DevBuf<int32_t> st_col(E2, s), st_src(E2, s);
+            sample_keep_staged(g, salt, thr, keep.get(), kpre.get(), st_col.get(), st_src.get(), s);
+            scan_exclusive_i32(kpre.get(), kpre.get(), NW, s);
+            positions_at_rows(g->row_ptr, n, E2, keep.get(), kpre.get(), rps.get(), degs.get(), s);
+            move_staged(E2, kpre.get(), st_col.get(), st_src.get(), cols.get(), srcs.get(), s);
+        }
         v_row = rps.get();
         v_col = cols.get();
         v_src = srcs.get();
@@ -2032,8 +2055,8 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     const int64_t E2 = 2 * m;
     if (n == 0 || E2 == 0) return b;
     const int64_t NW = (E2 + 63) / 64;
-    if (sampled)
-        b += rb(8 * NW) + rb(4 * (NW + 1)) + rb(4 * (n + 1)) + rb(4 * n) + 2 * rb(4 * E2) + scan_scratch_bytes(NW);
+    if (sampled)  // keep bits and prefix, rows, degrees, entries, staged entries
+        b += rb(8 * NW) + rb(4 * (NW + 1)) + rb(4 * (n + 1)) + rb(4 * n) + 4 * rb(4 * E2) + scan_scratch_bytes(NW);
     b += rb(n) + rb(8 * NW) + rb(4 * (NW + 1)) + scan_scratch_bytes(NW);  // degree classes, orientation bits
     b += rb(4 * (n + 1)) + rb(4 * n) + rb(4 * m);                  // rpO, d+, up lists
     b += 2 * rb(4 * (n + 1)) + 2 * rb(4 * n) + scan_scratch_bytes(n);  // heavy, code, d-, descriptor slots

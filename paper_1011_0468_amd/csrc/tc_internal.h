@@ -181,6 +181,13 @@ uint64_t sample_salt(uint64_t seed);
 // keep bits (one uint64 per 64 CSR entries) and per-word popcounts
 void sample_keep_bits(const tc_graph_s* g, uint64_t salt, uint64_t thr, uint64_t* bits, int32_t* wcnt,
                       hipStream_t s);
+// the same with the kept entries staged per range of 512 entries (st_col,
+// st_src: E2 entries each), then moved into place by move_staged once wcnt
+// is scanned into wpre
+void sample_keep_staged(const tc_graph_s* g, uint64_t salt, uint64_t thr, uint64_t* bits, int32_t* wcnt,
+                        int32_t* st_col, int32_t* st_src, hipStream_t s);
+void move_staged(int64_t E2, const int32_t* wpre, const int32_t* st_col, const int32_t* st_src, int32_t* col_out,
+                 int32_t* src_out, hipStream_t s);
 // rank of CSR position e among kept entries, for every row start: rp_out[x] (x in [0,n])
 void positions_at_rows(const int32_t* row_ptr, int64_t n, int64_t E2, const uint64_t* bits,
                        const int32_t* wpre, int32_t* rp_out, int32_t* deg_out, hipStream_t s);

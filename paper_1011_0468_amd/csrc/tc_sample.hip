@@ -102,6 +102,96 @@ __global__ void __launch_bounds__(256) k_compact(const int32_t* __restrict__ col
     }
 }
 
+// Keep bits with the kept entries staged: one wave per range of kStageWords
+// words (64 entries each).  The wave writes the range's keep words and their
+// popcounts, and packs the range's kept entries, in order, at the start of
+// the range's region of the staging arrays (entries [64 w0, 64 w0 + kept)),
+// with full-width stores.  Once the word counts are scanned, k_move_staged
+// copies each range's packed entries to their place, so no entry of the
+// graph is read twice and no store is one lane wide.
+constexpr int kStageWords = 8;
+
+__device__ __forceinline__ void wave_lds_order_s() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void __launch_bounds__(256) k_keep_stage(const int32_t* __restrict__ src, const int32_t* __restrict__ col,
+                                                     int64_t E2, uint64_t salt, uint64_t thr,
+                                                     uint64_t* __restrict__ bits, int32_t* __restrict__ wcnt,
+                                                     int32_t* __restrict__ st_col, int32_t* __restrict__ st_src) {
+    constexpr int RW = kStageWords;
+    __shared__ int32_t pack[4][2][RW * 64];
+    const int lane = __lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int32_t* pc = pack[wv][0];
+    int32_t* ps = pack[wv][1];
+    const uint64_t below = lanes_below();
+    const int64_t NW = (E2 + 63) / 64;
+    const int64_t nR = (NW + RW - 1) / RW;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + wv; r < nR; r += nwaves) {
+        const int64_t w0 = r * RW;
+        int32_t uu[RW], vv[RW];
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int64_t e = (w0 + i) * 64 + lane;
+            const bool in = e < E2;
+            uu[i] = in ? src[e] : 0;
+            vv[i] = in ? col[e] : 0;
+        }
+        int32_t cnt = 0;
+        uint64_t mine = 0;  // lane i < RW: word w0 + i
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int64_t e = (w0 + i) * 64 + lane;
+            const bool keep = e < E2 && edge_kept((uint32_t)uu[i], (uint32_t)vv[i], salt, thr);
+            const uint64_t b = ballot64(keep);
+            if (lane == i) mine = b;
+            if (keep) {
+                const int32_t q = cnt + (int32_t)__popcll(b & below);
+                pc[q] = vv[i];
+                ps[q] = uu[i];
+            }
+            cnt += (int32_t)__popcll(b);
+        }
+        if (lane < RW && w0 + lane < NW) {
+            bits[w0 + lane] = mine;
+            wcnt[w0 + lane] = (int32_t)__popcll(mine);
+        }
+        wave_lds_order_s();
+        for (int32_t q = lane; q < cnt; q += 64) {
+            st_col[w0 * 64 + q] = pc[q];
+            st_src[w0 * 64 + q] = ps[q];
+        }
+        wave_lds_order_s();  // read before the next range packs
+    }
+}
+
+// Each range's staged entries to positions wpre[w0] .. (wpre: exclusive scan
+// of the word counts, NW + 1 entries).
+__global__ void __launch_bounds__(256) k_move_staged(int64_t E2, const int32_t* __restrict__ wpre,
+                                                      const int32_t* __restrict__ st_col,
+                                                      const int32_t* __restrict__ st_src, int32_t* __restrict__ col_out,
+                                                      int32_t* __restrict__ src_out) {
+    constexpr int RW = kStageWords;
+    const int lane = __lane_id();
+    const int64_t NW = (E2 + 63) / 64;
+    const int64_t nR = (NW + RW - 1) / RW;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); r < nR; r += nwaves) {
+        const int64_t w0 = r * RW;
+        const int64_t w1 = w0 + RW < NW ? w0 + RW : NW;
+        const int32_t a = wpre[w0];
+        const int32_t cnt = wpre[w1] - a;
+        for (int32_t q = lane; q < cnt; q += 64) {
+            col_out[a + q] = st_col[w0 * 64 + q];
+            src_out[a + q] = st_src[w0 * 64 + q];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // unions of samples (batched seeds, fused requests)
 // ---------------------------------------------------------------------------
@@ -171,41 +261,82 @@ __device__ __forceinline__ int32_t nz_id(const int4* __restrict__ nzt, int64_t x
     return t.z + __popcll(r == 0 ? 0ull : (b & (~0ull >> (64 - r))));
 }
 
+// Orders one wave's LDS accesses (a wave's LDS operations complete in issue
+// order; only the compiler must not move accesses across).
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Words of g per range of k_compact_rep
+constexpr int kRepWords = 8;
+
 // Kept entries of the replicated space, in the padded layout's ids (k_nz_relabel
-// maps them to the union's final ids).  One wave per word of g for every
-// copy, so each entry of g is read once; the copies' keep words and prefixes
-// are loaded 64 at a time, one copy per lane, and taken with readlane.
+// maps them to the union's final ids).  One wave per range of kRepWords words
+// of g: the range's entries are read once and held in registers, and for
+// every copy the kept entries of the whole range, which are consecutive in
+// that copy's output, are packed in LDS and written with full-width stores
+// (one store per 64 kept entries instead of one per word and copy).  The
+// copies' keep words and prefixes are loaded 64 at a time (8 copies x 8
+// words, one per lane) and taken with readlane.
 __global__ void __launch_bounds__(256) k_compact_rep(const int32_t* __restrict__ col, const int32_t* __restrict__ src,
                                                       int64_t E2, int64_t NWp, int32_t K, int64_t npad,
                                                       const uint64_t* __restrict__ bits,
                                                       const int32_t* __restrict__ wpre, int32_t* __restrict__ col_out,
                                                       int32_t* __restrict__ src_out) {
+    constexpr int RW = kRepWords, CPL = 64 / RW;  // words per range, copies per load
+    __shared__ int32_t pack[4][2][RW * 64];
     const int lane = __lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int32_t* pc = pack[wv][0];
+    int32_t* ps = pack[wv][1];
     const uint64_t below = lanes_below();
-    const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t w = wave; w < NWp; w += nwaves) {
-        const int64_t e = w * 64 + lane;
-        const bool in = e < E2;
-        const int32_t v = in ? col[e] : 0, u = in ? src[e] : 0;
-        for (int32_t k0 = 0; k0 < K; k0 += 64) {
-            const int32_t kl = k0 + lane;
-            const int64_t wl = (int64_t)kl * NWp + w;
-            const uint64_t myb = kl < K ? bits[wl] : 0ull;
-            const int32_t myp = kl < K ? wpre[wl] : 0;
-            uint64_t any = ballot64(myb != 0);
-            while (any) {  // copies whose word keeps something, in order
-                const int j = __builtin_ctzll(any);
-                any &= any - 1;
-                const uint64_t bw = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(myb >> 32), j) << 32) |
-                                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)myb, j);
-                const int32_t pre = __builtin_amdgcn_readlane(myp, j);
+    const int64_t nR = (NWp + RW - 1) / RW;
+    for (int64_t r = wave; r < nR; r += nwaves) {
+        const int64_t w0 = r * RW;
+        int32_t vv[RW], uu[RW];
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int64_t e = (w0 + i) * 64 + lane;
+            const bool in = w0 + i < NWp && e < E2;
+            vv[i] = in ? col[e] : 0;
+            uu[i] = in ? src[e] : 0;
+        }
+        for (int32_t k0 = 0; k0 < K; k0 += CPL) {
+            const int32_t kl = k0 + lane / RW;
+            const int64_t wl = w0 + lane % RW;
+            const bool ok = kl < K && wl < NWp;  // words past NWp belong to no copy of this range
+            const uint64_t myb = ok ? bits[(int64_t)kl * NWp + wl] : 0ull;
+            const int32_t myp = ok ? wpre[(int64_t)kl * NWp + wl] : 0;
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
                 const int64_t k = k0 + j;
-                if ((bw >> lane) & 1ull) {  // set bits lie below E2
-                    const int32_t p = pre + __popcll(bw & below);
-                    col_out[p] = (int32_t)(k * npad + v);
-                    src_out[p] = (int32_t)(k * npad + u);
+                if (k >= K) break;
+                const int32_t base = __builtin_amdgcn_readlane(myp, j * RW);  // the copy's first kept entry here
+                int32_t cnt = 0;
+#pragma unroll
+                for (int i = 0; i < RW; ++i) {
+                    const int src_lane = j * RW + i;
+                    const uint64_t bw =
+                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(myb >> 32), src_lane) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)myb, src_lane);
+                    if ((bw >> lane) & 1ull) {  // set bits lie below E2
+                        const int32_t q = cnt + (int32_t)__popcll(bw & below);
+                        pc[q] = (int32_t)(k * npad + vv[i]);
+                        ps[q] = (int32_t)(k * npad + uu[i]);
+                    }
+                    cnt += (int32_t)__popcll(bw);
                 }
+                if (cnt == 0) continue;
+                wave_lds_order();
+                for (int32_t q = lane; q < cnt; q += 64) {
+                    col_out[base + q] = pc[q];
+                    src_out[base + q] = ps[q];
+                }
+                wave_lds_order();  // read before the next copy packs
             }
         }
     }
@@ -379,6 +510,23 @@ void sample_keep_bits(const tc_graph_s* g, uint64_t salt, uint64_t thr, uint64_t
               wcnt);
 }
 
+void sample_keep_staged(const tc_graph_s* g, uint64_t salt, uint64_t thr, uint64_t* bits, int32_t* wcnt,
+                        int32_t* st_col, int32_t* st_src, hipStream_t s) {
+    const int64_t E2 = 2 * g->m;
+    if (E2 == 0) return;
+    const int64_t nR = ((E2 + 63) / 64 + kStageWords - 1) / kStageWords;
+    TC_LAUNCH("sample_keep", k_keep_stage, dim3(grid_for(nR, 4)), dim3(256), 0, s, g->src, g->col, E2, salt, thr,
+              bits, wcnt, st_col, st_src);
+}
+
+void move_staged(int64_t E2, const int32_t* wpre, const int32_t* st_col, const int32_t* st_src, int32_t* col_out,
+                 int32_t* src_out, hipStream_t s) {
+    if (E2 == 0) return;
+    const int64_t nR = ((E2 + 63) / 64 + kStageWords - 1) / kStageWords;
+    TC_LAUNCH("compact", k_move_staged, dim3(grid_for(nR, 4)), dim3(256), 0, s, E2, wpre, st_col, st_src, col_out,
+              src_out);
+}
+
 void positions_at_rows(const int32_t* row_ptr, int64_t n, int64_t E2, const uint64_t* bits, const int32_t* wpre,
                        int32_t* rp_out, int32_t* deg_out, hipStream_t s) {
     TC_LAUNCH("rows_at", k_rows_at, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, row_ptr, n, E2, bits, wpre, rp_out,
@@ -464,7 +612,8 @@ void sample_union_replicas(const tc_graph_s* g, int32_t K, const uint64_t* salts
     DevBuf<int4> nzt(NV, s);
     TC_LAUNCH("nz_table", k_nz_table, dim3(grid_for(NV, 256)), dim3(256), 0, s, NV, npad, (const uint64_t*)nzb.get(),
               (const int32_t*)nzpre.get(), (const int32_t*)off, nzt.get());
-    TC_LAUNCH("compact_rep", k_compact_rep, dim3(grid_for(NWp, 4)), dim3(256), 0, s, (const int32_t*)g->col,
+    TC_LAUNCH("compact_rep", k_compact_rep, dim3(grid_for((NWp + kRepWords - 1) / kRepWords, 4)), dim3(256), 0, s,
+              (const int32_t*)g->col,
               (const int32_t*)g->src, E2, NWp, K, npad, (const uint64_t*)bits.get(), (const int32_t*)wpre.get(),
               out->col, out->src);
     if (total > 0)
