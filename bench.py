@@ -43,16 +43,20 @@ def _light_model_bytes(c, large):
     return c["model_bytes_large"] if large else c["model_bytes_small"]
 
 
-def _source_sha():
-    """Hash of the sources the counting kernels are compiled from."""
+COUNT_SOURCES = ("tc_count.hip", "tc_device.h")
+STREAM_SOURCES = ("tc_stream.hip", "tc_device.h")
+
+
+def _source_sha(sources=COUNT_SOURCES):
+    """Hash of the sources a kernel is compiled from (default: the counting kernels)."""
     h = hashlib.sha256()
-    for name in ("tc_count.hip", "tc_device.h"):
+    for name in sources:
         with open(os.path.join(ROOT, "paper_1011_0468_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel, workload, tunings):
+def _traffic(kernel, workload, tunings, sources=COUNT_SOURCES):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel source with the same launch parameters."""
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))
@@ -62,7 +66,7 @@ def _traffic(kernel, workload, tunings):
         rec = json.load(open(path))
     except Exception:
         return None
-    if rec.get("source_sha") != _source_sha() or rec.get("tunings") != tunings:
+    if rec.get("source_sha") != _source_sha(sources) or rec.get("tunings") != tunings:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -147,13 +151,104 @@ def batched(args):
     ms_single = (time.perf_counter() - t) * 1e3 / args.steps
     edges = sum(c["m"] for c in per)
     assert [c["triangles"] for c in per] == [c["triangles"] for c in one]
+
+    # the heavy multipliers c in {1/2, 1, 2} and the autotuner's choice (tuned
+    # on seed 1000, which is not in the batch), each timed on the same batch:
+    # the counts must not change, only the reported light/heavy split
+    def timed_batch(**kw):
+        for _ in range(max(1, args.warmup)):
+            tc.tc_estimate(g, p, seeds, num_groups=8, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pv, _, mv = tc.tc_estimate(g, p, seeds, num_groups=8, **kw)
+        torch.cuda.synchronize()
+        assert [c["triangles"] for c in pv] == [c["triangles"] for c in per] and mv == mom
+        return round((time.perf_counter() - t0) * 1e3 / args.steps, 3), sum(c["n_heavy"] for c in pv)
+    variants = {}
+    for a, b in ((1, 2), (1, 1), (2, 1)):
+        ms_v, nh = timed_batch(heavy=(a, b))
+        variants["%d/%d" % (a, b)] = {"ms": ms_v, "heavy_vertices_all_seeds": nh}
+    choice = tc.tc_autotune(g, p, seed=1000)
+    ms_t, nh_t = timed_batch(tuned=True)
+    variants["autotuned"] = {"ms": ms_t, "heavy_vertices_all_seeds": nh_t, "choice": choice}
     print(json.dumps({"metric": "batched sampled-graph edges/sec (64 seeds, one call)", "value": edges / (ms_batch / 1e3),
                       "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                       "ms_per_step": round(ms_batch, 3), "ms_64_single_calls": round(ms_single, 3),
                       "speedup_vs_single_calls": round(ms_single / ms_batch, 2), "median_of_means": mom,
+                      "heavy_multiplier_runs": variants,
                       "higher_is_better": True, "dtype": "int32", "data": "synthetic",
                       "config": {"workload": "cl20", "n": n, "m": g.info()["m"], "p": p, "seeds": 64, "groups": 8}}),
           flush=True)
+
+
+def latency_cl16k(args):
+    """Latency of the small configuration, Chung-Lu n = 16384 (avg degree 12,
+    beta 2.5): the exact count and the p = 0.25 estimate of seed 0, each call
+    timed on its own (it synchronises its stream) over 50 calls after 5
+    warm-up calls: median, min and max in microseconds.  Counts against the
+    oracle's stored values; the oracle's own time on the same two calls."""
+    import statistics
+    import torch
+    import synth
+    import paper_1011_0468_amd as tc
+    n, s, d = synth.workload("cl16k")
+    g = tc.tc_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    reps = max(50, args.steps)
+    calls = {"exact": lambda: tc.tc_count_exact(g),
+             "p=0.25": lambda: tc.tc_estimate(g, 0.25, [0])[0][0]}
+    out, got = {}, {}
+    for name, fn in calls.items():
+        for _ in range(max(5, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        us = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            got[name] = fn()
+            us.append((time.perf_counter() - t0) * 1e6)
+        out[name] = {"median_us": round(statistics.median(us), 1), "min_us": round(min(us), 1),
+                     "max_us": round(max(us), 1), "calls": reps}
+    golden = _load_golden("cl16k.json")
+    parity = None
+    if golden:
+        want = {c["p"]: c for c in golden["counts"]}
+        keys = ("triangles", "light", "heavy", "n_heavy", "m")
+        parity = all(got[name][k] == want[p][k] for name, p in (("exact", 1.0), ("p=0.25", 0.25)) for k in keys)
+    line = {"metric": "latency of the exact count on Chung-Lu n=16384 (one call, median)",
+            "value": out["exact"]["median_us"], "unit": "us", "n_gpus": 1, "steps": reps, "warmup": max(5, args.warmup),
+            "higher_is_better": False, "dtype": "int32", "data": "synthetic", "calls": out,
+            "parity_vs_oracle": parity, "config": {"workload": "cl16k", "n": n, "m": g.info()["m"]}}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_calls("cl16k", ((1.0, 0), (0.25, 0)), reps=20)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_calls(workload, legs, reps):
+    """The oracle (one pinned core) on the given (p, seed) legs, repeated reps
+    times: median microseconds per leg (sampling plus exact split count)."""
+    import statistics
+    import oracle
+    import synth
+    g = oracle.normalise(*synth.workload(workload))
+    allowed = sorted(os.sched_getaffinity(0))
+    pin = allowed[0]
+    os.sched_setaffinity(0, {pin})
+    try:
+        res = {}
+        for p, sd in legs:
+            us = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                gp = g if p == 1.0 else oracle.sample(g, p, sd)
+                oracle.count_split(gp, 1, 1)
+                us.append((time.perf_counter() - t0) * 1e6)
+            res["p=%g" % p] = round(statistics.median(us), 1)
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    return {"value": res["p=1"], "unit": "us", "cores": 1, "kind": "oracle", "per_leg_median_us": res,
+            "sample": "%s: the exact count and the p=0.25 sample + count of seed 0, %d times each, median"
+                      % (workload, reps), "pinned_cpu": pin, "nproc": len(allowed), "cpu_model": _cpu_model()}
 
 
 def adaptive(args):
@@ -491,8 +586,9 @@ def stream_workload(args):
                       "rel_error": (r["estimate"] / exact - 1.0) if exact else None, "parity_vs_oracle": parity,
                       "kernels": kern,
                       "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "stream_pass3",
-                                   "model_bytes_per_launch": p3_bytes},
+                                   "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                   "traffic": _traffic("stream_pass3", "rmat22", None, STREAM_SOURCES),
+                                   "kernel": "stream_pass3", "model_bytes_per_launch": p3_bytes},
                       "config": {"workload": "stream_rmat22", "n": info["n"], "m": m, "d": dd, "num_samples": S,
                                  "seed": args.seed}}), flush=True)
 
@@ -556,6 +652,9 @@ def main():
         return
     if args.workload == "heavy":
         heavy_stress(args)
+        return
+    if args.workload == "cl16k":
+        latency_cl16k(args)
         return
     if args.workload == "stream":
         stream_workload(args)

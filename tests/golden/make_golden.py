@@ -3,7 +3,7 @@
 Calls only the CPU oracle (oracle/) on inputs from the seeded generators
 (synth/); nothing here touches the device path.  Usage:
 
-    python tests/golden/make_golden.py rmat22 rmat22_splits cl20 rmat24 rmat24_count rmat22_top serve20 stream22
+    python tests/golden/make_golden.py rmat22 rmat22_splits cl20 rmat24 rmat24_count rmat22_top serve20 stream22 cl16k
 
 Each section writes tests/golden/<name>.json.
 """
@@ -134,6 +134,19 @@ def rmat22_top():
         out[str(h)] = {"m": int(len(sub[2]) // 2), "triangles": int(oracle.count(sub))}
     return {"workload": "R-MAT scale 22 (generator seed 1), subgraph induced by the top-h degree vertices",
             "blocks": out}
+
+
+def cl16k():
+    # the small Chung-Lu configuration: exact count and the p = 0.25 sample
+    # of seed 0, with the light/heavy split at c = 1
+    g = _graph("cl16k")
+    out = []
+    for p, seed in ((1.0, 0), (0.25, 0)):
+        gp = g if p == 1.0 else oracle.sample(g, p, seed)
+        r = oracle.count_split(gp, 1, 1)
+        r.update(p=p, seed=seed)
+        out.append(r)
+    return {"workload": "Chung-Lu n=16384, avg degree 12, beta 2.5, generator seed 1", "counts": out}
 
 
 def stream22():
