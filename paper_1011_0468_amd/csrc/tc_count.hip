@@ -51,6 +51,11 @@ constexpr unsigned kClassifyBlocks = 2048;
 
 // Entries of an iterated list processed by one work item.
 constexpr int kJL = 256;
+// Tiny items (k_light_tiny): at most kTinyKeys anchor keys and iterated
+// descriptors and kTinyPositions streamed positions, kTinyLanes lanes each
+constexpr int kTinyLanes = 8;
+constexpr int kTinyKeys = 8;
+constexpr int kTinyPositions = 64;
 // Largest anchor out-degree whose table the block kernel keeps in LDS.
 constexpr int kLdsDcap = 1024;
 // Strips of 64 positions per super-strip of the closure loop.
@@ -608,8 +613,9 @@ __device__ __forceinline__ void classify_vertex(int64_t x, const int32_t* __rest
                                                 const int32_t* __restrict__ dplus, const int64_t* __restrict__ Wu,
                                                 const unsigned long long* __restrict__ cw,
                                                 const int32_t* __restrict__ rpD, int32_t small_dmax,
-                                                int32_t* __restrict__ nsm, int32_t* __restrict__ nlg,
-                                                int32_t* __restrict__ nhg, int64_t (&st)[8], int64_t& dmax) {
+                                                int32_t* __restrict__ ntn, int32_t* __restrict__ nsm,
+                                                int32_t* __restrict__ nlg, int32_t* __restrict__ nhg,
+                                                int64_t (&st)[8], int64_t& dmax) {
     const int32_t c = code[x];
     const int32_t dp = dplus[x];
     if (c > 0) { st[0] += 1; st[1] += c; st[2] += (int64_t)c * (c - 1) / 2; }
@@ -623,7 +629,12 @@ __device__ __forceinline__ void classify_vertex(int64_t x, const int32_t* __rest
     st[3] += wu + wv;
     const bool small = dp <= small_dmax;
     const bool huge = dp > kLdsDcap;
-    nsm[x] = small ? cu + cv : 0;
+    // tiny: at most kTinyKeys keys and descriptors and kTinyPositions
+    // positions per item, so one item per group of kTinyLanes lanes
+    const bool tiny = small && dp <= kTinyKeys && (cv == 0 || nv <= kTinyKeys) && wu <= kTinyPositions &&
+                      wv <= kTinyPositions;
+    ntn[x] = tiny ? cu + cv : 0;
+    nsm[x] = small && !tiny ? cu + cv : 0;
     nlg[x] = (!small && !huge) ? cu + cv : 0;
     nhg[x] = huge ? cu + cv : 0;
     if (small) { st[4] += bytes; st[6] += cu + cv; }
@@ -638,13 +649,13 @@ __global__ void __launch_bounds__(256) k_classify(int64_t n, const int32_t* __re
                                                    const int32_t* __restrict__ dplus, const int64_t* __restrict__ Wu,
                                                    const unsigned long long* __restrict__ cw,
                                                    const int32_t* __restrict__ rpD, int32_t small_dmax,
-                                                   int32_t* __restrict__ nsm,
+                                                   int32_t* __restrict__ ntn, int32_t* __restrict__ nsm,
                                                    int32_t* __restrict__ nlg, int32_t* __restrict__ nhg,
                                                    int64_t* __restrict__ part) {
     int64_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sources, out, wedges, probes, bytes_s, bytes_l, items_s, items_l
     int64_t dmax = 0;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
-        classify_vertex(x, code, dplus, Wu, cw, rpD, small_dmax, nsm, nlg, nhg, st, dmax);
+        classify_vertex(x, code, dplus, Wu, cw, rpD, small_dmax, ntn, nsm, nlg, nhg, st, dmax);
     __shared__ int64_t red[4][9];
     const int wv_ = threadIdx.x >> 6;
 #pragma unroll
@@ -709,8 +720,9 @@ __global__ void __launch_bounds__(256) k_classify_union(int64_t n, const int32_t
                                                          const int64_t* __restrict__ Gx,
                                                          const unsigned long long* __restrict__ cw,
                                                          const int32_t* __restrict__ rpD, int32_t small_dmax,
-                                                         int32_t* __restrict__ nsm, int32_t* __restrict__ nlg,
-                                                         int32_t* __restrict__ nhg, int64_t* __restrict__ acc) {
+                                                         int32_t* __restrict__ ntn, int32_t* __restrict__ nsm,
+                                                         int32_t* __restrict__ nlg, int32_t* __restrict__ nhg,
+                                                         int64_t* __restrict__ acc) {
     const int64_t windows = (n + 255) / 256;
     const int64_t per = (windows + gridDim.x - 1) / gridDim.x;
     const int64_t w0 = (int64_t)blockIdx.x * per;
@@ -727,7 +739,7 @@ __global__ void __launch_bounds__(256) k_classify_union(int64_t n, const int32_t
         }
         const int64_t x = xs + threadIdx.x;
         if (x < n) {
-            classify_vertex(x, code, dplus, Wu, cw, rpD, small_dmax, nsm, nlg, nhg, st, dmax);
+            classify_vertex(x, code, dplus, Wu, cw, rpD, small_dmax, ntn, nsm, nlg, nhg, st, dmax);
             if (code[x] > 0) gth += Gx[x];
         }
     }
@@ -736,18 +748,21 @@ __global__ void __launch_bounds__(256) k_classify_union(int64_t n, const int32_t
 
 // items of anchor x: (x, r) for the u-major ranges r of N+(x), then (~x, r)
 // for the ranges r of x's v-major descriptors
-// The item lists of all three bins in one pass: an anchor's items go to the
-// list of its bin (small, large or huge, exclusive) at its bin's prefix.
-__global__ void k_items(int64_t n, const int32_t* __restrict__ nsm, const int32_t* __restrict__ nlg,
-                        const int32_t* __restrict__ nhg, const int32_t* __restrict__ sbase,
+// The item lists of all four bins in one pass: an anchor's items go to the
+// list of its bin (tiny, small, large or huge, exclusive) at its bin's prefix.
+__global__ void k_items(int64_t n, const int32_t* __restrict__ ntn, const int32_t* __restrict__ nsm,
+                        const int32_t* __restrict__ nlg, const int32_t* __restrict__ nhg,
+                        const int32_t* __restrict__ tbase, const int32_t* __restrict__ sbase,
                         const int32_t* __restrict__ lbase, const int32_t* __restrict__ hbase,
                         const int32_t* __restrict__ dplus, const int64_t* __restrict__ Wu,
                         const unsigned long long* __restrict__ cw, const int32_t* __restrict__ rpD,
-                        int2* __restrict__ items_s, int2* __restrict__ items_l, int2* __restrict__ items_h) {
+                        int2* __restrict__ items_t, int2* __restrict__ items_s, int2* __restrict__ items_l,
+                        int2* __restrict__ items_h) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         int2* items;
         int32_t b;
-        if (nsm[x]) { items = items_s; b = sbase[x]; }
+        if (ntn[x]) { items = items_t; b = tbase[x]; }
+        else if (nsm[x]) { items = items_s; b = sbase[x]; }
         else if (nlg[x]) { items = items_l; b = lbase[x]; }
         else if (nhg[x]) { items = items_h; b = hbase[x]; }
         else continue;
@@ -1233,6 +1248,113 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
 // sees the LDS address space and emits ds_* instructions), or in a global
 // scratch slice per block when they do not fit (GLOBAL = true).  After
 // staging, each wave closes a quarter of the item's positions.
+// Broadcast of lane K of each group of 8 lanes, and the exchange with the
+// lane X apart, inside the group (ds_swizzle bit mode on 32-lane halves).
+template <int K>
+__device__ __forceinline__ int32_t grp_lane(int32_t v) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x18 | (K << 5));
+}
+template <int X>
+__device__ __forceinline__ int32_t grp_xor(int32_t v) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x1F | (X << 10));
+}
+template <int K = 0>
+__device__ __forceinline__ void grp_all(int32_t v, int32_t (&out)[kTinyLanes]) {
+    out[K] = grp_lane<K>(v);
+    if constexpr (K + 1 < kTinyLanes) grp_all<K + 1>(v, out);
+}
+
+// Tiny items (at most 8 keys, 8 iterated descriptors and 64 positions): one
+// group of 8 lanes per item, 8 items per wave and step, no tables.  Lane k of
+// a group loads key k of the anchor's out-list and descriptor k (start and
+// length of a streamed list); the group shares them through lane swizzles, and
+// then each lane takes one position per round, finds its list among the 8 by
+// comparing with the lists' ends, reads the streamed entry and compares it
+// with the 8 keys.  Wave-per-item work costs some 180 instructions per item,
+// mostly its LDS table and staging; here a round of 8 items costs about as
+// much as one.
+template <bool UNION>
+__global__ void __launch_bounds__(256) k_light_tiny(const int2* __restrict__ items,
+                                                     const int32_t* __restrict__ n_items_dev,
+                                                     const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
+                                                     const int32_t* __restrict__ rpD,
+                                                     const unsigned long long* __restrict__ cw,
+                                                     const int2* __restrict__ packU, const int2* __restrict__ packD,
+                                                     const int32_t* __restrict__ comp, int64_t* __restrict__ acc) {
+    constexpr int G = kTinyLanes;
+    static_assert(G == 8 && kTinyKeys <= G, "one key and one descriptor per lane of a group");
+    const int lane = __lane_id();
+    const int pos = lane & (G - 1);
+    const int64_t gw = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t n_items = n_items_dev[0];
+    int64_t total = 0;
+    for (int64_t it0 = gw * (64 / G); it0 < n_items; it0 += nw * (64 / G)) {
+        const int64_t it = it0 + lane / G;
+        const bool has = it < n_items;
+        // the item: anchor x, its keys N+(x) and the iterated descriptors
+        const int2 item = has ? items[it] : make_int2(0, 0);
+        const bool kind_u = item.x >= 0;
+        const int32_t x = kind_u ? item.x : ~item.x;
+        const int32_t rs = has ? rpO[x] : 0;
+        const int32_t d = has ? rpO[x + 1] - rs : 0;
+        int32_t llen = d;
+        const int2* L = packU + rs;
+        if (has && !kind_u) {
+            const int32_t ds = rpD[x];
+            L = packD + ds;
+            llen = cw_end(cw[x]) - ds;
+        }
+        const int32_t key = pos < d ? colO[rs + pos] : -1;
+        const int2 e = pos < llen ? L[pos] : make_int2(0, 0);
+        const int32_t ln = e.y > 0 ? e.y : 0;  // 0: the pair is closed from the other side
+        int32_t kk[G], lk[G], sk[G];
+        grp_all(key, kk);
+        grp_all(ln, lk);
+        grp_all(e.x, sk);
+        int32_t ek[G];  // end of list k among the item's positions
+        int32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            run += lk[k];
+            ek[k] = run;
+        }
+        const int32_t W = has ? run : 0;
+        int32_t cnt = 0;
+        for (int32_t c0 = 0; ballot64(c0 < W); c0 += G) {
+            const int32_t g = c0 + pos;
+            const bool on = g < W;
+            // the first list whose end lies past g (empty lists end where the one before does)
+            int32_t at = 0;
+            bool found = false;
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const bool here = !found && ek[k] > g;
+                at = here ? sk[k] + (g - (ek[k] - lk[k])) : at;
+                found = found || here;
+            }
+            const int32_t v = on ? colO[at] : -1;
+            bool hit = false;
+#pragma unroll
+            for (int k = 0; k < G; ++k) hit = hit || (v == kk[k]);
+            cnt += on && hit ? 1 : 0;
+        }
+        if (UNION) {
+            cnt += grp_xor<1>(cnt);
+            cnt += grp_xor<2>(cnt);
+            cnt += grp_xor<4>(cnt);
+            if (pos == 0 && has && cnt)
+                atomicAdd((unsigned long long*)&acc[(int64_t)comp[x] * kCountSlots + kTL], (unsigned long long)cnt);
+        } else {
+            total += cnt;
+        }
+    }
+    if (!UNION) {
+        total = wave_sum(total);
+        if (lane == 0 && total) atomicAdd((unsigned long long*)&acc[kTL], (unsigned long long)total);
+    }
+}
+
 template <bool GLOBAL, bool UNION>
 __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ items,
                                                       const int32_t* __restrict__ n_items_dev,
@@ -1887,23 +2009,25 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     launch_wide(k_work_wide<4>, 0, 128, "work_w4", res_w[0]);
     launch_wide(k_work_wide<8>, 1, 256, "work_w8", res_w[1]);
     launch_wide(k_work_wide<16>, 2, 512, "work_w16", res_w[2]);
-    DevBuf<int32_t> nsm(n + 1, s), nlg(n + 1, s), nhg(n + 1, s);
+    DevBuf<int32_t> ntn(n + 1, s), nsm(n + 1, s), nlg(n + 1, s), nhg(n + 1, s);
     const unsigned cgrid = std::min<unsigned>(grid_for(n, 256), kClassifyBlocks);
     DevBuf<int64_t> cpart((size_t)cgrid * 9, s);
     if (!un)
         TC_LAUNCH("classify", k_classify, dim3(cgrid), dim3(256), 0, s, n, (const int32_t*)code.get(),
                   (const int32_t*)dplus.get(), (const int64_t*)Wu.get(), (const unsigned long long*)cwp,
-                  (const int32_t*)rpD.get(), cfg.small_dmax, nsm.get(), nlg.get(), nhg.get(), cpart.get());
+                  (const int32_t*)rpD.get(), cfg.small_dmax, ntn.get(), nsm.get(), nlg.get(), nhg.get(),
+                  cpart.get());
     else
         TC_LAUNCH("classify", k_classify_union, dim3(cgrid), dim3(256), 0, s, n, comp, (const int32_t*)code.get(),
                   (const int32_t*)dplus.get(), (const int64_t*)Wu.get(), (const int64_t*)gxp,
-                  (const unsigned long long*)cwp, (const int32_t*)rpD.get(), cfg.small_dmax, nsm.get(), nlg.get(),
-                  nhg.get(), acc);
-    DevBuf<int32_t> sbase(n + 1, s), lbase(n + 1, s), hbase(n + 1, s), hpos(n + 1, s);
+                  (const unsigned long long*)cwp, (const int32_t*)rpD.get(), cfg.small_dmax, ntn.get(), nsm.get(),
+                  nlg.get(), nhg.get(), acc);
+    DevBuf<int32_t> sbase(n + 1, s), lbase(n + 1, s), hbase(n + 1, s), hpos(n + 1, s), tbase(n + 1, s);
     {
         const int32_t* in[4] = {nsm.get(), nlg.get(), nhg.get(), heavy.get()};
         int32_t* out[4] = {sbase.get(), lbase.get(), hbase.get(), hpos.get()};
         scan_exclusive_i32_x4(in, out, n, s);
+        scan_exclusive_i32(ntn.get(), tbase.get(), n, s);
     }
 
     // 4. light phase: three bins by anchor out-degree; each kernel is a
@@ -1911,13 +2035,29 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     const int32_t maxd = g->max_deg;  // bounds every d+ of every sample
     const LightPlan plan = light_plan(g->m, maxd, cfg);
     // the item lists of the launched bins (a bin that is not launched has no items)
-    DevBuf<int2> items_s(items_max, s), items_l(plan.dcap_lds ? items_max : 0, s),
+    DevBuf<int2> items_t(items_max, s), items_s(items_max, s), items_l(plan.dcap_lds ? items_max : 0, s),
         items_h(plan.dcap_global ? items_max : 0, s);
-    TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)nsm.get(),
-              (const int32_t*)nlg.get(), (const int32_t*)nhg.get(), (const int32_t*)sbase.get(),
-              (const int32_t*)lbase.get(), (const int32_t*)hbase.get(), (const int32_t*)dplus.get(),
-              (const int64_t*)Wu.get(), (const unsigned long long*)cwp, (const int32_t*)rpD.get(), items_s.get(),
-              items_l.get(), items_h.get());
+    TC_LAUNCH("items", k_items, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)ntn.get(),
+              (const int32_t*)nsm.get(), (const int32_t*)nlg.get(), (const int32_t*)nhg.get(),
+              (const int32_t*)tbase.get(), (const int32_t*)sbase.get(), (const int32_t*)lbase.get(),
+              (const int32_t*)hbase.get(), (const int32_t*)dplus.get(), (const int64_t*)Wu.get(),
+              (const unsigned long long*)cwp, (const int32_t*)rpD.get(), items_t.get(), items_s.get(), items_l.get(),
+              items_h.get());
+    {
+        static const int resident = [] {
+            int r = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_light_tiny<false>, 256, 0) != hipSuccess || r < 1)
+                r = 1;
+            (void)hipGetLastError();
+            return r;
+        }();
+        const int64_t blocks = (int64_t)num_cus() * std::min<int32_t>(cfg.light_blocks_per_cu, resident);
+        auto kernel = un ? k_light_tiny<true> : k_light_tiny<false>;
+        TC_LAUNCH("light_tiny", kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const int2*)items_t.get(),
+                  (const int32_t*)tbase.get() + n, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
+                  (const int32_t*)rpD.get(), (const unsigned long long*)cwp, (const int2*)packU.get(),
+                  (const int2*)packD.get(), comp, acc);
+    }
     {
         const DevBuf<int2>& items = items_s;
         // a persistent grid larger than what stays resident would run its last
@@ -2062,7 +2202,8 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     b += 2 * rb(4 * (n + 1)) + 2 * rb(4 * n) + scan_scratch_bytes(n);  // heavy, code, d-, descriptor slots
     b += rb(16 * n) + 2 * rb(8 * n) + rb(12 * (n + 1));            // rowQ, Wu, cw, wide-list vertices
     b += rb(8 * m) + rb(8 * (cfg.vmajor_cap > 0 ? m : 1));         // packed descriptors
-    b += 7 * rb(4 * (n + 1)) + scan_x4_scratch_bytes(n);                       // item counts and bases
+    b += 9 * rb(4 * (n + 1)) + scan_x4_scratch_bytes(n) + scan_scratch_bytes(n);  // item counts and bases
+    b += rb(8 * (2 * n + E2 / kJL + 2));                                           // tiny item list
     b += rb(8 * 9 * (int64_t)std::min<int64_t>((n + 255) / 256, kClassifyBlocks));  // classification partials
     const int64_t items_max = 2 * n + E2 / kJL + 2;
     b += rb(8 * items_max);

@@ -272,19 +272,20 @@ __device__ __forceinline__ void wave_lds_order() {
 // Words of g per range of k_compact_rep
 constexpr int kRepWords = 8;
 
-// Kept entries of the replicated space, in the padded layout's ids (k_nz_relabel
-// maps them to the union's final ids).  One wave per range of kRepWords words
+// Kept entries of the replicated space, written with the union's final ids
+// (nz_id of the padded layout's id).  One wave per range of kRepWords words
 // of g: the range's entries are read once and held in registers, and for
 // every copy the kept entries of the whole range, which are consecutive in
-// that copy's output, are packed in LDS and written with full-width stores
-// (one store per 64 kept entries instead of one per word and copy).  The
-// copies' keep words and prefixes are loaded 64 at a time (8 copies x 8
-// words, one per lane) and taken with readlane.
+// that copy's output, are packed in LDS, relabelled by full-width table
+// gathers and written with full-width stores (one store per 64 kept entries
+// instead of one per word and copy).  The copies' keep words and prefixes
+// are loaded 64 at a time (8 copies x 8 words, one per lane) and taken with
+// readlane.
 __global__ void __launch_bounds__(256) k_compact_rep(const int32_t* __restrict__ col, const int32_t* __restrict__ src,
                                                       int64_t E2, int64_t NWp, int32_t K, int64_t npad,
                                                       const uint64_t* __restrict__ bits,
-                                                      const int32_t* __restrict__ wpre, int32_t* __restrict__ col_out,
-                                                      int32_t* __restrict__ src_out) {
+                                                      const int32_t* __restrict__ wpre, const int4* __restrict__ nzt,
+                                                      int32_t* __restrict__ col_out, int32_t* __restrict__ src_out) {
     constexpr int RW = kRepWords, CPL = 64 / RW;  // words per range, copies per load
     __shared__ int32_t pack[4][2][RW * 64];
     const int lane = __lane_id();
@@ -333,22 +334,12 @@ __global__ void __launch_bounds__(256) k_compact_rep(const int32_t* __restrict__
                 if (cnt == 0) continue;
                 wave_lds_order();
                 for (int32_t q = lane; q < cnt; q += 64) {
-                    col_out[base + q] = pc[q];
-                    src_out[base + q] = ps[q];
+                    col_out[base + q] = nz_id(nzt, pc[q]);
+                    src_out[base + q] = nz_id(nzt, ps[q]);
                 }
                 wave_lds_order();  // read before the next copy packs
             }
         }
-    }
-}
-
-// the kept entries' padded-layout ids mapped to the union's final ids
-__global__ void k_nz_relabel(int64_t E, const int4* __restrict__ nzt, int32_t* __restrict__ col,
-                             int32_t* __restrict__ src) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = col[e], r = src[e];
-        col[e] = nz_id(nzt, c);
-        src[e] = nz_id(nzt, r);
     }
 }
 
@@ -615,10 +606,7 @@ void sample_union_replicas(const tc_graph_s* g, int32_t K, const uint64_t* salts
     TC_LAUNCH("compact_rep", k_compact_rep, dim3(grid_for((NWp + kRepWords - 1) / kRepWords, 4)), dim3(256), 0, s,
               (const int32_t*)g->col,
               (const int32_t*)g->src, E2, NWp, K, npad, (const uint64_t*)bits.get(), (const int32_t*)wpre.get(),
-              out->col, out->src);
-    if (total > 0)
-        TC_LAUNCH("nz_relabel", k_nz_relabel, dim3(grid_for(total, 256)), dim3(256), 0, s, total,
-                  (const int4*)nzt.get(), out->col, out->src);
+              (const int4*)nzt.get(), out->col, out->src);
     TC_LAUNCH("comp_edges", k_comp_edges, dim3(ceil_div(K, 256)), dim3(256), 0, s, K, (const int32_t*)off,
               (const int32_t*)out->row_ptr, mk);
 }
