@@ -328,6 +328,7 @@ void graph_release(tc_graph_s* g) {
     dev_free(g->col, g->home);
     dev_free(g->src, g->home);
     dev_free(g->deg, g->home);
+    if (g->ncls) dev_free(g->ncls, g->home);
     delete g;
 }
 

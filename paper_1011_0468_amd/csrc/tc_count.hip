@@ -80,11 +80,19 @@ __global__ void k_deg_class(int64_t n, const int32_t* __restrict__ degp, uint8_t
         cls[x] = (uint8_t)deg_class(degp[x]);
 }
 
+// the degree class of every entry's neighbour
+__global__ void k_neighbour_class(int64_t E2, const int32_t* __restrict__ col, const int32_t* __restrict__ degp,
+                                  uint8_t* __restrict__ ncls) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E2; e += (int64_t)gridDim.x * blockDim.x)
+        ncls[e] = (uint8_t)deg_class(degp[col[e]]);
+}
+
 // Per CSR entry (u, v) of a kept edge: "up" if (deg u, u) < (deg v, v).  Each
 // kept undirected edge has exactly one up entry, in the row of its
-// lower-ranked end.  The random per-neighbour lookup reads the degree class
-// (one byte per vertex, cache-resident), and only ties of classes above 15
-// (about 7% of R-MAT's entries) read the exact degrees; the entry streams
+// lower-ranked end.  The neighbour's degree class comes from ncls (one byte
+// per entry, in order) when the graph itself is counted, else from a random
+// lookup of the class array (one byte per vertex); only ties of classes above
+// 15 (about 7% of R-MAT's entries) read the exact degrees; the entry streams
 // bypass the cache.  E2 bounds the buffers; E2_dev (if not null) holds the
 // number of valid entries, which may be smaller (a compacted sample in buffers
 // sized for the full graph): words past it get zero bits.  Each wave takes 4
@@ -93,6 +101,7 @@ __global__ void k_deg_class(int64_t n, const int32_t* __restrict__ degp, uint8_t
 __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__ src, const int32_t* __restrict__ col,
                                                       int64_t E2, const int32_t* __restrict__ E2_dev,
                                                       const uint8_t* __restrict__ cls,
+                                                      const uint8_t* __restrict__ ncls,
                                                       const int32_t* __restrict__ degp, uint64_t* __restrict__ ubits,
                                                       int32_t* __restrict__ ucnt) {
     const int lane = __lane_id();
@@ -107,6 +116,7 @@ __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__
     for (int64_t w = NWv + (wave * 64 + lane); w < NW; w += nwaves * 64) ucnt[w] = 0;
     for (int64_t w0 = wave * 4; w0 < NWv; w0 += nwaves * 4) {
         int32_t u[4], v[4];
+        uint32_t nc[4];
         bool in[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -116,12 +126,13 @@ __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__
             const int32_t a = __builtin_nontemporal_load(src + ec), c = __builtin_nontemporal_load(col + ec);
             u[k] = in[k] ? a : 0;  // vertex 0 exists whenever a count runs
             v[k] = in[k] ? c : 0;
+            nc[k] = ncls ? (uint32_t)__builtin_nontemporal_load(ncls + ec) : 0u;
         }
         uint32_t cu[4], cv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             cu[k] = cls[u[k]];
-            cv[k] = cls[v[k]];
+            cv[k] = ncls ? (in[k] ? nc[k] : cls[0]) : cls[v[k]];
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -1960,8 +1971,10 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     DevBuf<int32_t> upre(NW + 1, s);
     DevBuf<uint8_t> cls(n, s);
     TC_LAUNCH("deg_class", k_deg_class, dim3(grid_for(n, 256)), dim3(256), 0, s, n, degp, cls.get());
+    // the counted graph's own neighbour classes when it is the built graph
+    const uint8_t* ncls = !sampled && !un ? g->ncls : nullptr;
     TC_LAUNCH("orient_bits", k_orient_bits, dim3(grid_for(NW, 16)), dim3(256), 0, s, v_src, v_col, E2, E2_dev,
-              (const uint8_t*)cls.get(), degp, ubits.get(), upre.get());
+              (const uint8_t*)cls.get(), ncls, degp, ubits.get(), upre.get());
     scan_exclusive_i32(upre.get(), upre.get(), NW, s);
     const int32_t* mp_dev = upre.get() + NW;  // number of up entries = m'
     DevBuf<int32_t> rpO(n + 1, s), dplus(n, s);
@@ -2187,6 +2200,14 @@ void counts_from_slots(const int64_t* hacc, tc_counts* out) {
     res.model_bytes_small = hacc[kBytesSmall];
     res.model_bytes_large = hacc[kBytesLarge];
     *out = res;
+}
+
+void neighbour_classes(tc_graph_s* g, hipStream_t s) {
+    const int64_t E2 = 2 * g->m;
+    if (E2 == 0) return;
+    g->ncls = (uint8_t*)dev_alloc((size_t)E2, s);
+    TC_LAUNCH("neighbour_class", k_neighbour_class, dim3(grid_for(E2, 256)), dim3(256), 0, s, E2,
+              (const int32_t*)g->col, (const int32_t*)g->deg, g->ncls);
 }
 
 int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const CountConfig& cfg) {

@@ -245,14 +245,17 @@ int64_t build_csr_bytes(int64_t n, int64_t num_pairs) {
     }
     b += rb(4 * (N + 1)) + scan_scratch_bytes(N);                              // unique positions
     b += rb(4 * (n + 1)) + 2 * rb(4 * N) + rb(4 * n) + scan_scratch_bytes(n);  // the CSR (2m <= N)
+    b += rb(N);                                                                 // neighbour classes
     return b;
 }
 
 int build_csr(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst, hipStream_t s, tc_graph_s* g) {
     PhaseScope ph("csr");
     const int nb = key_bits_half(n);
-    if (2 * nb <= 32) return build_csr_t<uint32_t>(n, num_pairs, src, dst, nb, s, g);
-    return build_csr_t<uint64_t>(n, num_pairs, src, dst, nb, s, g);
+    const int bad = 2 * nb <= 32 ? build_csr_t<uint32_t>(n, num_pairs, src, dst, nb, s, g)
+                                 : build_csr_t<uint64_t>(n, num_pairs, src, dst, nb, s, g);
+    if (!bad) neighbour_classes(g, s);
+    return bad;
 }
 
 }  // namespace tc

@@ -134,6 +134,7 @@ struct tc_graph_s {
     int32_t* col = nullptr;       // [2m]
     int32_t* src = nullptr;       // [2m] row index of each CSR entry
     int32_t* deg = nullptr;       // [n]
+    uint8_t* ncls = nullptr;      // [2m] degree class of each entry's neighbour (graphs built by build_csr)
     hipStream_t home = nullptr;   // stream the buffers were allocated on
 };
 
@@ -170,6 +171,10 @@ int build_csr(int64_t n, int64_t num_pairs, const int32_t* src_dev, const int32_
               hipStream_t s, tc_graph_s* g);
 // Sum of the sizes of every allocation build_csr makes (region_bytes each).
 int64_t build_csr_bytes(int64_t n, int64_t num_pairs);
+// g->ncls of a built graph: the degree class of every entry's neighbour, so
+// that the orientation of the graph itself reads it in order instead of
+// gathering it per entry (tc_count.hip)
+void neighbour_classes(tc_graph_s* g, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Sampling (tc_sample.hip)
