@@ -51,7 +51,8 @@ typedef enum {
 
 /* Opaque graph handle: owns a device CSR (row_ptr int32[n+1], col int32[2m]
    with each list sorted ascending, the row index of every CSR entry, and
-   deg int32[n]) until tc_graph_free. */
+   deg int32[n]; a graph from tc_build_csr also keeps one byte per entry, a
+   class of the neighbour's degree that orders degrees) until tc_graph_free. */
 typedef struct tc_graph_s* tc_graph;
 
 /* Light/heavy threshold (section 3.2 uses deg <= m^(1/2) for light).  A vertex
