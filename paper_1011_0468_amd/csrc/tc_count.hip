@@ -80,11 +80,12 @@ __global__ void k_deg_class(int64_t n, const int32_t* __restrict__ degp, uint8_t
         cls[x] = (uint8_t)deg_class(degp[x]);
 }
 
-// the degree class of every entry's neighbour
-__global__ void k_neighbour_class(int64_t E2, const int32_t* __restrict__ col, const int32_t* __restrict__ degp,
+// the degree class of every entry's neighbour, gathered from the class array
+// (one byte per vertex: a quarter of the degrees' footprint)
+__global__ void k_neighbour_class(int64_t E2, const int32_t* __restrict__ col, const uint8_t* __restrict__ cls,
                                   uint8_t* __restrict__ ncls) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E2; e += (int64_t)gridDim.x * blockDim.x)
-        ncls[e] = (uint8_t)deg_class(degp[col[e]]);
+        ncls[e] = cls[col[e]];
 }
 
 // Per CSR entry (u, v) of a kept edge: "up" if (deg u, u) < (deg v, v).  Each
@@ -151,9 +152,11 @@ __global__ void __launch_bounds__(256) k_orient_bits(const int32_t* __restrict__
     }
 }
 
-// int32 words of one 4-wave block's table, list staging and flags (16-byte multiple)
+// int32 words of one 4-wave block's table, list staging and flags (one byte
+// per position, 64 kU per wave; 16-byte multiple).  With the largest table
+// (dcap = 1024) a block takes 19.5 KB, so 8 blocks fit a CU's LDS.
 __host__ __device__ inline int64_t large_block_words(int32_t dcap) {
-    return (4 * (int64_t)dcap + 2 * kJL + 1 + 256 * kU + 3) / 4 * 4;
+    return (4 * (int64_t)dcap + 2 * kJL + 1 + 64 * kU + 3) / 4 * 4;
 }
 
 // Heavy block: U is stored padded to a multiple of the MFMA macro tile edge.
@@ -950,13 +953,13 @@ __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const 
 // none empty, so P is strictly increasing.  On entry jlo owns position g0 - 1
 // (or g0), on exit position g0 + 64U - 1.  When no list starts inside the
 // super-strip every lane owns jlo.  Otherwise the lists starting inside it (at
-// most 64U, those after jlo) flag their start offsets in `mark` (64U ints of
+// most 64U, those after jlo) flag their start offsets in `mark` (64U bytes of
 // per-wave memory, all zero between calls), and the owner of position
 // g0 + 64k + lane is jlo plus the number of flags at offsets <= 64k + lane:
 // one ballot and one mbcnt per strip of 64.  Whole wave.
 template <int U, bool GLOBAL>
 __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D, int nl, int32_t g0, int32_t b,
-                                              const int32_t* __restrict__ colO, int32_t* mark, int lane, int& jlo,
+                                              const int32_t* __restrict__ colO, uint8_t* mark, int lane, int& jlo,
                                               int32_t (&x)[U], uint64_t (&vm)[U]) {
     // every lane loads (lanes past b read colO[0], which exists whenever there
     // are positions) and nothing consumes the loaded values before the probe,
@@ -1015,7 +1018,7 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D
 template <int U, bool GLOBAL, bool SHORT>
 __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D, int nl, int32_t a, int32_t b,
                                               const int32_t* __restrict__ colO, const int32_t* tab, int lg,
-                                              int32_t* mark, int lane) {
+                                              uint8_t* mark, int lane) {
     // a, b and nl are wave-uniform; saying so makes every exit of the
     // pipelined loop below a scalar branch.  Otherwise the loop is compiled
     // as a divergent one whose early exit reaches the loop head with the
@@ -1170,7 +1173,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
                                                       const int2* __restrict__ packU, const int2* __restrict__ packD,
                                                       const int32_t* __restrict__ comp, int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 4 * DS;                                     // buckets of 4 slots, load <= 1/4
-    constexpr int ROW = (HS_MAX + 2 * kJL + 1 + 64 * kU + 3) / 4 * 4;  // keeps every row 16-byte aligned
+    constexpr int ROW = (HS_MAX + 2 * kJL + 1 + 16 * kU + 3) / 4 * 4;  // keeps every row 16-byte aligned
     constexpr int KR = (DS + 63) / 64;                                 // keys per lane
     constexpr int LR = (kJL + 63) / 64;                                // list descriptors per lane
     __shared__ __attribute__((aligned(16))) int32_t lds[4][ROW];
@@ -1179,9 +1182,8 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
     int32_t* tab = lds[w];
     int32_t* P = tab + HS_MAX;
     int32_t* D = P + kJL + 1;
-    int32_t* mark = D + kJL;
-#pragma unroll
-    for (int k = 0; k < kU; ++k) mark[lane + 64 * k] = 0;  // flags stay zero between super-strips
+    uint8_t* mark = reinterpret_cast<uint8_t*>(D + kJL);  // 64 kU bytes
+    if (lane < 16 * kU) reinterpret_cast<int32_t*>(mark)[lane] = 0;  // flags stay zero between super-strips
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
     const int64_t n_items = n_items_dev[0];
@@ -1377,7 +1379,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
                                                       const int32_t* __restrict__ comp, int64_t* __restrict__ acc) {
     extern __shared__ __attribute__((aligned(16))) int32_t dyn[];
     __shared__ int32_t red[5];
-    // layout: hash table (4 next_pow2(d) <= 4 dcap slots), P (kJL + 1), D (kJL), flags (4 x 64 kU)
+    // layout: hash table (4 next_pow2(d) <= 4 dcap slots), P (kJL + 1), D (kJL), flags (4 x 64 kU bytes)
     const int64_t per_block = large_block_words(dcap);
     int32_t* base = GLOBAL ? gscratch + (int64_t)blockIdx.x * per_block : dyn;
     int32_t* tab = base;
@@ -1386,9 +1388,8 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
     const int t = threadIdx.x;
     const int w = t >> 6;
     const int lane = __lane_id();
-    int32_t* mark = D + kJL + 64 * kU * w;
-#pragma unroll
-    for (int k = 0; k < kU; ++k) mark[lane + 64 * k] = 0;  // flags stay zero between super-strips
+    uint8_t* mark = reinterpret_cast<uint8_t*>(D + kJL) + 64 * kU * w;  // 64 kU bytes per wave
+    if (lane < 16 * kU) reinterpret_cast<int32_t*>(mark)[lane] = 0;  // flags stay zero between super-strips
     const int64_t n_items = n_items_dev[0];
     int64_t total = 0;
     int32_t cur = 0;  // component of the closures in total
@@ -2205,9 +2206,12 @@ void counts_from_slots(const int64_t* hacc, tc_counts* out) {
 void neighbour_classes(tc_graph_s* g, hipStream_t s) {
     const int64_t E2 = 2 * g->m;
     if (E2 == 0) return;
+    DevBuf<uint8_t> cls(g->n, s);
+    TC_LAUNCH("deg_class", k_deg_class, dim3(grid_for(g->n, 256)), dim3(256), 0, s, g->n, (const int32_t*)g->deg,
+              cls.get());
     g->ncls = (uint8_t*)dev_alloc((size_t)E2, s);
     TC_LAUNCH("neighbour_class", k_neighbour_class, dim3(grid_for(E2, 256)), dim3(256), 0, s, E2,
-              (const int32_t*)g->col, (const int32_t*)g->deg, g->ncls);
+              (const int32_t*)g->col, (const uint8_t*)cls.get(), g->ncls);
 }
 
 int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const CountConfig& cfg) {

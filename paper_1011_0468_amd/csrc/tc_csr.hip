@@ -245,7 +245,7 @@ int64_t build_csr_bytes(int64_t n, int64_t num_pairs) {
     }
     b += rb(4 * (N + 1)) + scan_scratch_bytes(N);                              // unique positions
     b += rb(4 * (n + 1)) + 2 * rb(4 * N) + rb(4 * n) + scan_scratch_bytes(n);  // the CSR (2m <= N)
-    b += rb(N);                                                                 // neighbour classes
+    b += rb(N) + rb(n);                                                         // neighbour classes
     return b;
 }
 
