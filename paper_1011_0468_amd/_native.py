@@ -8,6 +8,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "libtc.so")
+TORCH_ALLOC_PATH = os.path.join(HERE, "libtc_torch_alloc.so")
 
 TC_OK, TC_ERR_INVALID, TC_ERR_OOM, TC_ERR_DEVICE, TC_ERR_OVERFLOW, TC_ERR_BUDGET = range(6)
 STATUS_NAMES = {0: "TC_OK", 1: "TC_ERR_INVALID", 2: "TC_ERR_OOM", 3: "TC_ERR_DEVICE",
@@ -160,8 +161,35 @@ def load():
     L.tc_server_destroy.restype = None
     L.tc_last_error.argtypes = []
     L.tc_last_error.restype = ctypes.c_char_p
+    _install_torch_allocator(L)
     _lib = L
     return L
+
+
+_torch_alloc = None  # the shim and its two function pointers, kept alive while installed
+
+
+def _install_torch_allocator(L):
+    """Route the library's device allocations through PyTorch's caching
+    allocator (tc_set_allocator with the C functions of libtc_torch_alloc.so:
+    no Python runs per allocation), so that one pool serves the caller's
+    tensors and the library's buffers."""
+    global _torch_alloc
+    if not os.path.exists(TORCH_ALLOC_PATH):
+        raise RuntimeError("libtc_torch_alloc.so is not built (run __graft_entry__.build())")
+    import torch  # noqa: F401  (loads libc10_hip before the shim)
+    A = ctypes.CDLL(TORCH_ALLOC_PATH)
+    fa = ALLOC_FN(ctypes.cast(A.tc_torch_alloc, ctypes.c_void_p).value)
+    ff = FREE_FN(ctypes.cast(A.tc_torch_free, ctypes.c_void_p).value)
+    rc = L.tc_set_allocator(fa, ff, None)
+    if rc != 0:
+        raise RuntimeError("tc_set_allocator refused the torch allocator (status %d)" % rc)
+    _torch_alloc = (A, fa, ff)
+
+
+def allocator():
+    """"torch" while PyTorch's caching allocator serves the library."""
+    return "torch" if _torch_alloc is not None else "library"
 
 
 def check(status):

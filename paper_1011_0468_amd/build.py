@@ -38,7 +38,27 @@ def build(jobs=8, verbose=False):
     tmp = OUT + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, OUT)
+    build_torch_alloc()
     return OUT
+
+
+TORCH_ALLOC = os.path.join(HERE, "libtc_torch_alloc.so")
+
+
+def build_torch_alloc():
+    """The allocator shim (host code): tc_torch_alloc / tc_torch_free over
+    PyTorch's caching allocator, installed by the binding with tc_set_allocator."""
+    import torch
+    tdir = os.path.dirname(torch.__file__)
+    tmp = TORCH_ALLOC + ".tmp"
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    subprocess.check_call([HIPCC, "-O2", "-std=c++17", "-fPIC", "-shared", "-x", "c++", "-D__HIP_PLATFORM_AMD__",
+                           "-I" + os.path.join(tdir, "include"), "-I" + os.path.join(rocm, "include"),
+                           os.path.join(CSRC, "torch_alloc.cpp"),
+                           "-L" + os.path.join(tdir, "lib"), "-lc10_hip", "-lc10",
+                           "-Wl,-rpath," + os.path.join(tdir, "lib"), "-o", tmp])
+    os.replace(tmp, TORCH_ALLOC)
+    return TORCH_ALLOC
 
 
 if __name__ == "__main__":
