@@ -883,6 +883,16 @@ __device__ __forceinline__ int bucket_bits(int32_t d) {
     return lg;
 }
 
+// Buckets for d keys in a region of 2^lgmax buckets (lgmax >= bucket_bits(d)):
+// 2^lg >= 2 d where the region allows it.  A lookup that misses in a full home
+// bucket walks on, one LDS read per bucket; at one key per bucket on average
+// about 2% of the buckets are full, so most waves of 64 probes take that walk,
+// and at half a key per bucket only some 0.2% are.
+__device__ __forceinline__ int table_bits(int32_t d, int lgmax) {
+    const int lg = bucket_bits(2 * d);
+    return lg < lgmax ? lg : lgmax;
+}
+
 // largest j in [0, d-1] with P[j] <= g  (P non-decreasing, P[0] = 0 <= g)
 __device__ __forceinline__ int find_list(const int32_t* P, int d, int32_t g) {
     int lo = 0, hi = d - 1;
@@ -1173,6 +1183,8 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
                                                       const int2* __restrict__ packU, const int2* __restrict__ packD,
                                                       const int32_t* __restrict__ comp, int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 4 * DS;                                     // buckets of 4 slots, load <= 1/4
+    static_assert((DS & (DS - 1)) == 0 && DS >= 16, "DS: a power of two");
+    constexpr int kLgDS = __builtin_ctz(DS);                           // the table region holds 2^kLgDS buckets
     constexpr int ROW = (HS_MAX + 2 * kJL + 1 + 16 * kU + 3) / 4 * 4;  // keeps every row 16-byte aligned
     constexpr int KR = (DS + 63) / 64;                                 // keys per lane
     constexpr int LR = (kJL + 63) / 64;                                // list descriptors per lane
@@ -1232,7 +1244,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
                     cur = c;
                 }
             }
-            const int lg = bucket_bits(d);
+            const int lg = table_bits(d, kLgDS);
             const int hs = 4 << lg;
             for (int i = lane; i < hs; i += 64) tab[i] = -1;
             if (lane == 0) P[0] = 0;
@@ -1379,8 +1391,9 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
                                                       const int32_t* __restrict__ comp, int64_t* __restrict__ acc) {
     extern __shared__ __attribute__((aligned(16))) int32_t dyn[];
     __shared__ int32_t red[5];
-    // layout: hash table (4 next_pow2(d) <= 4 dcap slots), P (kJL + 1), D (kJL), flags (4 x 64 kU bytes)
+    // layout: hash table (4 x 2^lg <= 4 dcap slots), P (kJL + 1), D (kJL), flags (4 x 64 kU bytes)
     const int64_t per_block = large_block_words(dcap);
+    const int lgcap = __builtin_ctz((uint32_t)dcap);  // dcap: a power of two, the table region's buckets
     int32_t* base = GLOBAL ? gscratch + (int64_t)blockIdx.x * per_block : dyn;
     int32_t* tab = base;
     int32_t* P = base + 4 * dcap;
@@ -1413,7 +1426,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         else { const int32_t ds = rpD[x]; L = packD + ds; llen = cw_end(cw[x]) - ds; }
         const int32_t j0 = item.y * kJL;
         const int32_t cnt = min(kJL, llen - j0);
-        const int lg = bucket_bits(d);
+        const int lg = table_bits(d, lgcap);
         const int hs = 4 << lg;
         for (int i = t; i < hs; i += 256) tab[i] = -1;
         if (t == 0) P[0] = 0;
