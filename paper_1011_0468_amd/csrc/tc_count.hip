@@ -860,9 +860,17 @@ __device__ __forceinline__ uint32_t hslot(int32_t w, int lg) {
 // The anchor's out-list is kept in a bucketed open-addressing table: 2^lg
 // buckets of 4 slots (one 16-byte LDS read each), sized so that at most a
 // quarter of the slots are used.  A key goes to the first bucket with a free
-// slot along its probe sequence (home bucket, then the next ones); slots only
-// ever change from empty (-1) to full, so a lookup can stop at the first
-// bucket that holds the key or an empty slot.
+// slot along its probe sequence (home bucket, then the next ones).  An insert
+// that finds all four slots of a bucket taken marks that bucket as passed
+// over (the sign bit of its last slot; vertex ids are below 2^31 - 1, so a
+// marked slot never reads as empty, -1) before it moves on.  Slots only ever
+// change from empty to a key and from a key to the marked key, so after the
+// inserts a key sits in its home bucket or further along a run of marked
+// buckets, and a lookup stops at the first bucket that holds it or is not
+// marked.
+constexpr int32_t kPassed = (int32_t)0x80000000;  // mark on the last slot of a passed-over bucket
+constexpr int32_t kKeyBits = 0x7FFFFFFF;
+
 __device__ __forceinline__ void hash_insert(int32_t* tab, int lg, int32_t v) {
     const uint32_t mask = (1u << lg) - 1;
     uint32_t bk = hslot(v, lg) & mask;
@@ -870,8 +878,9 @@ __device__ __forceinline__ void hash_insert(int32_t* tab, int lg, int32_t v) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int32_t prev = atomicCAS(&tab[4 * bk + s], -1, v);
-            if (prev == -1 || prev == v) return;
+            if (prev == -1 || (prev & kKeyBits) == v) return;
         }
+        atomicOr(&tab[4 * bk + 3], kPassed);
         bk = (bk + 1) & mask;
     }
 }
@@ -884,10 +893,11 @@ __device__ __forceinline__ int bucket_bits(int32_t d) {
 }
 
 // Buckets for d keys in a region of 2^lgmax buckets (lgmax >= bucket_bits(d)):
-// 2^lg >= 2 d where the region allows it.  A lookup that misses in a full home
-// bucket walks on, one LDS read per bucket; at one key per bucket on average
-// about 2% of the buckets are full, so most waves of 64 probes take that walk,
-// and at half a key per bucket only some 0.2% are.
+// 2^lg >= 2 d where the region allows it.  A lookup that misses in a
+// passed-over home bucket walks on, one LDS read per bucket; at one key per
+// bucket on average about one bucket in 300 is passed over, so a good share
+// of the waves of 256 probes take that walk, and at half a key per bucket
+// almost none.
 __device__ __forceinline__ int table_bits(int32_t d, int lgmax) {
     const int lg = bucket_bits(2 * d);
     return lg < lgmax ? lg : lgmax;
@@ -906,11 +916,10 @@ __device__ __forceinline__ int find_list(const int32_t* P, int d, int32_t g) {
 
 // Membership tests of the keys x[k] of the lanes in the wave mask vm[k]
 // against the bucketed table; returns the number of hits in the whole wave
-// (wave-uniform).  One 16-byte read per key resolves it unless the bucket is
-// full without it.  Slots of a bucket fill in order (an insert tries slot s
-// only after finding slots 0..s-1 full) and never empty, so a bucket has a
-// free slot iff its last slot is free.  Every x[k] is a vertex id (>= 0), also
-// in lanes outside vm[k].
+// (wave-uniform).  One 16-byte read per key resolves it unless its home
+// bucket was passed over by an insert and does not hold it (about one bucket
+// in 300 at one key per bucket on average, one in 5000 at 0.6).  Every x[k]
+// is a vertex id (>= 0), also in lanes outside vm[k].
 template <int U>
 __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const int32_t (&x)[U],
                                               const uint64_t (&vm)[U]) {
@@ -929,14 +938,15 @@ __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const 
     for (int k = 0; k < U; ++k) {
         const int32_t v = x[k];
         // one compare per slot straight into a wave mask (no per-lane booleans)
-        const uint64_t hit =
-            (ballot64(e[k].x == v) | ballot64(e[k].y == v) | ballot64(e[k].z == v) | ballot64(e[k].w == v)) & vm[k];
-        const uint64_t full = ballot64(e[k].w >= 0);
+        const uint64_t hit = (ballot64(e[k].x == v) | ballot64(e[k].y == v) | ballot64(e[k].z == v) |
+                              ballot64((e[k].w & kKeyBits) == v)) &
+                             vm[k];
+        const uint64_t passed = ballot64(e[k].w < -1);  // marked last slot
         found += (int32_t)__popcll(hit);
-        live[k] = vm[k] & full & ~hit;
+        live[k] = vm[k] & passed & ~hit;
         any |= live[k];
     }
-    if (any) {  // rare: home bucket full without the key
+    if (any) {  // rare: home bucket passed over and without the key
         const int lane = __lane_id();
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -947,8 +957,8 @@ __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const 
                     bk[k] = (bk[k] + 1) & mask;
                     const int4 f = t4[bk[k]];
                     const int32_t v = x[k];
-                    if (f.x == v || f.y == v || f.z == v || f.w == v) { hitl = 1; on = false; }
-                    else if (f.w < 0) on = false;
+                    if (f.x == v || f.y == v || f.z == v || (f.w & kKeyBits) == v) { hitl = 1; on = false; }
+                    else if (f.w >= -1) on = false;  // not passed over: the key is not further on
                 }
                 found += (int32_t)__popcll(ballot64(hitl != 0));
             }
