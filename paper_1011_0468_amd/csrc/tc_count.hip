@@ -1593,8 +1593,8 @@ constexpr int kHRow = kHK + 16;  // LDS row stride: 16-lane groups of 16-byte re
 // consecutive k-bytes starting at 16 (l / 32); A and B use the same
 // k-permutation.  The epilogue masks C with U and adds into T_H.  Macro tiles
 // are enumerated column by column (t = J (J + 1) / 2 + I) and dealt to the 8
-// XCDs in contiguous ranges, so blocks of one XCD share the U^T panels of
-// their columns in that XCD's L2.
+// XCDs in contiguous ranges of equal work, so blocks of one XCD share the U^T
+// panels of their columns in that XCD's L2.
 // Masked sum of one 128 x 128 macro tile (I, J), I <= J, of C = U U over the
 // k-blocks [128 I, 128 J + 128) (U strictly upper triangular, hp x hp):
 // this thread's share.  As / Bs: the block's LDS staging.
@@ -1678,8 +1678,26 @@ __device__ __forceinline__ int64_t mfma_tile(const uint8_t* __restrict__ U, cons
 // consecutive k-bytes starting at 16 (l / 32); A and B use the same
 // k-permutation.  The epilogue masks C with U and adds into T_H.  Macro tiles
 // are enumerated column by column (t = J (J + 1) / 2 + I) and dealt to the 8
-// XCDs in contiguous ranges, so blocks of one XCD share the U^T panels of
-// their columns in that XCD's L2.
+// XCDs in contiguous ranges of equal work, so blocks of one XCD share the U^T
+// panels of their columns in that XCD's L2.
+// Work of the macro tiles before tile t in column-major order (t = J (J + 1) /
+// 2 + I): tile (I, J) takes J - I + 1 k-steps, so the columns before J take
+// J (J + 1) (J + 2) / 6 and the tiles (0..I-1, J) I (J + 1) - I (I - 1) / 2.
+// Returns the first tile whose preceding work reaches B (0 <= B <= the total
+// work of nm columns); nm columns hold nm (nm + 1) / 2 tiles.
+__device__ __forceinline__ int64_t tile_at_work(int64_t B, int64_t nm) {
+    auto cols = [](int64_t J) { return J * (J + 1) * (J + 2) / 6; };
+    int64_t J = (int64_t)cbrt(6.0 * (double)B);
+    if (J > nm) J = nm;
+    while (J > 0 && cols(J) > B) --J;
+    while (J < nm && cols(J + 1) <= B) ++J;
+    if (J >= nm) return nm * (nm + 1) / 2;
+    const int64_t r = B - cols(J);  // work still to pass inside column J (< its J (J + 1) / 2 + J + 1)
+    int64_t I = 0, w = 0;
+    while (I <= J && w < r) { w += J - I + 1; ++I; }
+    return J * (J + 1) / 2 + I;  // I = J + 1 is the next column's first tile
+}
+
 __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ U, const uint8_t* __restrict__ UT,
                                                      const int32_t* __restrict__ h_dev, int32_t hmax,
                                                      int64_t* __restrict__ acc) {
@@ -1693,10 +1711,14 @@ __global__ void __launch_bounds__(256) k_heavy_mfma(const uint8_t* __restrict__ 
     const int lane = __lane_id();
     const int64_t xcd = blockIdx.x & 7;
     const int64_t per_xcd = gridDim.x >> 3;
-    const int64_t chunk = (ntiles + 7) / 8;
-    const int64_t t_end = min(ntiles, (xcd + 1) * chunk);
+    // each XCD takes a contiguous range of equal work (the later columns
+    // hold longer tiles: an equal count of tiles gave the last XCD 1.5 times
+    // its share)
+    const int64_t work = nm * (nm + 1) * (nm + 2) / 6;
+    const int64_t t_begin = tile_at_work(xcd * work / 8, nm);
+    const int64_t t_end = xcd == 7 ? ntiles : tile_at_work((xcd + 1) * work / 8, nm);
     int64_t total = 0;
-    for (int64_t tt = xcd * chunk + (blockIdx.x >> 3); tt < t_end; tt += per_xcd) {
+    for (int64_t tt = t_begin + (blockIdx.x >> 3); tt < t_end; tt += per_xcd) {
         int64_t J = (int64_t)((sqrt(8.0 * (double)tt + 1.0) - 1.0) * 0.5);
         while (J * (J + 1) / 2 > tt) --J;
         while ((J + 1) * (J + 2) / 2 <= tt) ++J;
