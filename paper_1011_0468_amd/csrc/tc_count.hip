@@ -2026,8 +2026,10 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     DevBuf<int32_t> rpO(n + 1, s), dplus(n, s);
     positions_at_rows(v_row, n, E2, ubits.get(), upre.get(), rpO.get(), dplus.get(), s);
     DevBuf<int32_t> colO(g->m, s);  // m' <= m
-    DevBuf<int2> packU(g->m, s);    // one descriptor per up entry, cleared by the compaction
-    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), nullptr, s, E2_dev, packU.get());
+    // one descriptor per up entry: the anchor work writes every entry of every
+    // light source's list, and only those lists are read
+    DevBuf<int2> packU(g->m, s);
+    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), nullptr, s, E2_dev, nullptr);
 
     // 3. classification; anchor work (each light source's N+(u) in rank
     //    order, one descriptor per pair); item lists
