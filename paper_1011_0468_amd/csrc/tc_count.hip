@@ -1210,7 +1210,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
     int32_t* P = tab + HS_MAX;
     int32_t* D = P + kJL + 1;
     uint8_t* mark = reinterpret_cast<uint8_t*>(D + kJL);  // 64 kU bytes
-    if (lane < 16 * kU) reinterpret_cast<int32_t*>(mark)[lane] = 0;  // flags stay zero between super-strips
+    for (int i = lane; i < 16 * kU; i += 64) reinterpret_cast<int32_t*>(mark)[i] = 0;  // flags stay zero between super-strips
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
     const int64_t n_items = n_items_dev[0];
@@ -1417,7 +1417,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
     const int w = t >> 6;
     const int lane = __lane_id();
     uint8_t* mark = reinterpret_cast<uint8_t*>(D + kJL) + 64 * kU * w;  // 64 kU bytes per wave
-    if (lane < 16 * kU) reinterpret_cast<int32_t*>(mark)[lane] = 0;  // flags stay zero between super-strips
+    for (int i = lane; i < 16 * kU; i += 64) reinterpret_cast<int32_t*>(mark)[i] = 0;  // flags stay zero between super-strips
     const int64_t n_items = n_items_dev[0];
     int64_t total = 0;
     int32_t cur = 0;  // component of the closures in total
