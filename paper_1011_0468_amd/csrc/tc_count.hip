@@ -1261,7 +1261,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
             }
             const int lg = table_bits(d, kLgDS);
             const int hs = 4 << lg;
-            for (int i = lane; i < hs; i += 64) tab[i] = -1;
+            for (int i = lane; i < hs / 4; i += 64) reinterpret_cast<int4*>(tab)[i] = make_int4(-1, -1, -1, -1);
             if (lane == 0) P[0] = 0;
             wave_lds_sync();
 #pragma unroll
@@ -1443,7 +1443,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         const int32_t cnt = min(kJL, llen - j0);
         const int lg = table_bits(d, lgcap);
         const int hs = 4 << lg;
-        for (int i = t; i < hs; i += 256) tab[i] = -1;
+        for (int i = t; i < hs / 4; i += 256) reinterpret_cast<int4*>(tab)[i] = make_int4(-1, -1, -1, -1);
         if (t == 0) P[0] = 0;
         __syncthreads();
         build_hash<256>(rs, d, colO, tab, lg, t);
