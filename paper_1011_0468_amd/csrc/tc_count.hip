@@ -2034,7 +2034,7 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     // one descriptor per up entry: the anchor work writes every entry of every
     // light source's list, and only those lists are read
     DevBuf<int2> packU(g->m, s);
-    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), nullptr, s, E2_dev, nullptr);
+    compact_kept(v_col, v_src, E2, ubits.get(), upre.get(), colO.get(), nullptr, s, E2_dev);
 
     // 3. classification; anchor work (each light source's N+(u) in rank
     //    order, one descriptor per pair); item lists

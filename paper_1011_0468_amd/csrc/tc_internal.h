@@ -197,11 +197,10 @@ void move_staged(int64_t E2, const int32_t* wpre, const int32_t* st_col, const i
 void positions_at_rows(const int32_t* row_ptr, int64_t n, int64_t E2, const uint64_t* bits,
                        const int32_t* wpre, int32_t* rp_out, int32_t* deg_out, hipStream_t s);
 // compaction of kept entries (col and src, each optional on output); E2 bounds
-// the buffers, E2_dev (if not null) the entries that can have bits set;
-// zero_out (if not null) receives (0, 0) at every compacted position
+// the buffers, E2_dev (if not null) the entries that can have bits set
 void compact_kept(const int32_t* col, const int32_t* src, int64_t E2, const uint64_t* bits,
                   const int32_t* wpre, int32_t* col_out, int32_t* src_out, hipStream_t s,
-                  const int32_t* E2_dev = nullptr, int2* zero_out = nullptr);
+                  const int32_t* E2_dev = nullptr);
 
 // ---------------------------------------------------------------------------
 // Counting core (tc_count.hip)

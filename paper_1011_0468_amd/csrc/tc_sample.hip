@@ -64,8 +64,7 @@ __global__ void k_rows_at(const int32_t* __restrict__ row_ptr, int64_t n, int64_
 __global__ void __launch_bounds__(256) k_compact(const int32_t* __restrict__ col, const int32_t* __restrict__ src,
                                                   int64_t E2, const int32_t* __restrict__ E2_dev,
                                                   const uint64_t* __restrict__ bits, const int32_t* __restrict__ wpre,
-                                                  int32_t* __restrict__ col_out, int32_t* __restrict__ src_out,
-                                                  int2* __restrict__ zero_out) {
+                                                  int32_t* __restrict__ col_out, int32_t* __restrict__ src_out) {
     const int lane = __lane_id();
     const int64_t valid = E2_dev ? (int64_t)E2_dev[0] : E2;  // entries past it have no bits set
     const int64_t NW = (valid + 63) / 64;
@@ -96,7 +95,6 @@ __global__ void __launch_bounds__(256) k_compact(const int32_t* __restrict__ col
                 const int32_t p = pre[k] + __popcll(bw[k] & below);
                 col_out[p] = cv[k];
                 if (src_out) src_out[p] = sv[k];
-                if (zero_out) zero_out[p] = make_int2(0, 0);
             }
         }
     }
@@ -525,10 +523,10 @@ void positions_at_rows(const int32_t* row_ptr, int64_t n, int64_t E2, const uint
 }
 
 void compact_kept(const int32_t* col, const int32_t* src, int64_t E2, const uint64_t* bits, const int32_t* wpre,
-                  int32_t* col_out, int32_t* src_out, hipStream_t s, const int32_t* E2_dev, int2* zero_out) {
+                  int32_t* col_out, int32_t* src_out, hipStream_t s, const int32_t* E2_dev) {
     if (E2 == 0) return;
     TC_LAUNCH("compact", k_compact, dim3(grid_for((E2 + 63) / 64, 16)), dim3(256), 0, s, col, src, E2, E2_dev, bits,
-              wpre, col_out, src_out, zero_out);
+              wpre, col_out, src_out);
 }
 
 }  // namespace tc
