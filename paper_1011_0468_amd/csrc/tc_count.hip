@@ -210,41 +210,36 @@ __device__ __forceinline__ bool vmajor(int32_t len, int32_t dv, int32_t vcap) {
     return len <= dv && dv <= vcap;
 }
 
-// per vertex: heavy flag and code = d+(x) if x is a light source (light,
-// d+ >= 2) else 0 (in a union of components, m' is that of x's component:
-// mk[comp[x]])
+// Per vertex, everything the light phase needs of it: the heavy flag; code =
+// d+(x) if x is a light source (light, d+ >= 2), else 0 (in a union of
+// components, m' is that of x's component: mk[comp[x]]); rowQ[x] = (start of
+// N+(x), code ? d+ : ~d+, deg, 0), what the anchor work gathers of a vertex in
+// one 16-byte load; rpD[x], the first slot of x's v-major descriptors: the
+// in-degrees d- = deg - d+ of the vertices before x, that is x's row start in
+// the counted graph (row) minus its start in the up lists (rpO); and
+// cw[x] = rpD[x] << 32 (see claim_vmajor).  Also clears the counts of the
+// three wide-list classes, wide[c * (n + 1)].
 __global__ void k_vertex_prep(int64_t n, const int32_t* __restrict__ degp, const int32_t* __restrict__ dplus,
                               const int32_t* __restrict__ mp_dev, const int32_t* __restrict__ comp,
-                              const int64_t* __restrict__ mk, int32_t ha, int32_t hb, int32_t* __restrict__ heavy,
-                              int32_t* __restrict__ code) {
+                              const int64_t* __restrict__ mk, int32_t ha, int32_t hb,
+                              const int32_t* __restrict__ rpO, const int32_t* __restrict__ row,
+                              int32_t* __restrict__ heavy, int32_t* __restrict__ code, int32_t* __restrict__ rpD,
+                              int4* __restrict__ rowQ, unsigned long long* __restrict__ cw,
+                              int32_t* __restrict__ wide) {
     const int64_t mp = comp ? 0 : mp_dev[0];
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t dg = degp[x];
-        const bool hv = dg > 0 && is_heavy(dg, comp ? mk[comp[x]] : mp, ha, hb);
-        heavy[x] = hv ? 1 : 0;
-        const int32_t dp = dplus[x];
-        code[x] = !hv && dp >= 2 ? dp : 0;
-    }
-}
-
-// rowQ[x] = (start of N+(x), code ? d+ : ~d+, deg, 0): everything the anchor
-// work needs of a vertex in one 16-byte load; rpD[x], the first slot of x's
-// v-major descriptors: the in-degrees d- = deg - d+ of the vertices before x,
-// that is x's row start in the counted graph (row) minus its start in the up
-// lists (rpO); cw[x] = rpD[x] << 32 (see claim_vmajor)
-// (also clears the counts of the three wide-list classes, wide[c * (n + 1)])
-__global__ void k_row_q(int64_t n, const int32_t* __restrict__ rpO, const int32_t* __restrict__ code,
-                        const int32_t* __restrict__ dplus, const int32_t* __restrict__ degp,
-                        const int32_t* __restrict__ row, int32_t* __restrict__ rpD, int4* __restrict__ rowQ,
-                        unsigned long long* __restrict__ cw, int32_t* __restrict__ wide) {
     if (blockIdx.x == 0 && threadIdx.x < 3) wide[threadIdx.x * (n + 1)] = 0;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t r = rpO[x];
         const int32_t dslot = row[x] - r;
         rpD[x] = dslot;
         if (x == n) break;
-        const int32_t c = code[x];
-        rowQ[x] = make_int4(r, c ? c : ~dplus[x], degp[x], 0);
+        const int32_t dg = degp[x];
+        const bool hv = dg > 0 && is_heavy(dg, comp ? mk[comp[x]] : mp, ha, hb);
+        heavy[x] = hv ? 1 : 0;
+        const int32_t dp = dplus[x];
+        const int32_t c = !hv && dp >= 2 ? dp : 0;
+        code[x] = c;
+        rowQ[x] = make_int4(r, c ? c : ~dp, dg, 0);
         cw[x] = (unsigned long long)(uint32_t)dslot << 32;
     }
 }
@@ -2040,20 +2035,18 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     //    order, one descriptor per pair); item lists
     const int32_t vcap = cfg.vmajor_cap;
     DevBuf<int32_t> heavy(n + 1, s), code(n, s), rpD(n + 1, s);
-    TC_LAUNCH("vertex_prep", k_vertex_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, n, degp,
-              (const int32_t*)dplus.get(), mp_dev, comp, un ? un->mk : (const int64_t*)nullptr, cfg.heavy_num,
-              cfg.heavy_den, heavy.get(), code.get());
-    PhaseScope ph_light("light");
     DevBuf<int4> rowQ(n, s);
     DevBuf<int64_t> Wu(n, s), cw(n, s);
     DevBuf<int32_t> wide(3 * (n + 1), s);  // vertices with d+ in (128, 256], (256, 512], > 512; counts first
+    unsigned long long* cwp = reinterpret_cast<unsigned long long*>(cw.get());
+    TC_LAUNCH("vertex_prep", k_vertex_prep, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n, degp,
+              (const int32_t*)dplus.get(), mp_dev, comp, un ? un->mk : (const int64_t*)nullptr, cfg.heavy_num,
+              cfg.heavy_den, (const int32_t*)rpO.get(), v_row, heavy.get(), code.get(), rpD.get(), rowQ.get(), cwp,
+              wide.get());
+    PhaseScope ph_light("light");
     DevBuf<int64_t> Gx(un ? n : 0, s);  // per-list gather statistic (unions)
     int64_t* gxp = un ? Gx.get() : nullptr;
     DevBuf<int2> packD(vcap > 0 ? g->m : 1, s);  // v-major descriptors, rpD[v].. for vertex v
-    unsigned long long* cwp = reinterpret_cast<unsigned long long*>(cw.get());
-    TC_LAUNCH("row_q", k_row_q, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)rpO.get(),
-              (const int32_t*)code.get(), (const int32_t*)dplus.get(), degp, v_row, rpD.get(), rowQ.get(),
-              cwp, wide.get());
     TC_LAUNCH("work", k_work_lanes, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int4*)rowQ.get(),
               colO.get(), vcap, packU.get(), packD.get(), cwp, Wu.get(), gxp, wide.get(), acc);
     // longer lists by register class, persistent grids of one round of
