@@ -210,33 +210,49 @@ __device__ __forceinline__ bool vmajor(int32_t len, int32_t dv, int32_t vcap) {
     return len <= dv && dv <= vcap;
 }
 
-// Per vertex, everything the light phase needs of it: the heavy flag; code =
-// d+(x) if x is a light source (light, d+ >= 2), else 0 (in a union of
-// components, m' is that of x's component: mk[comp[x]]); rowQ[x] = (start of
+// Up entries before CSR position e of the counted graph: the word prefix of
+// the orientation bits plus the set bits below e in its word (E2 bounds the
+// buffers; positions at or past the valid entries have no bits below them).
+__device__ __forceinline__ int32_t up_before(int64_t e, int64_t E2, const uint64_t* __restrict__ ubits,
+                                             const int32_t* __restrict__ upre) {
+    if (e >= E2) return upre[(E2 + 63) >> 6];
+    const int r = (int)(e & 63);
+    const uint64_t below = r == 0 ? 0ull : (ubits[e >> 6] & (~0ull >> (64 - r)));
+    return upre[e >> 6] + __popcll(below);
+}
+
+// Per vertex, everything the light phase needs of it: the start of its up
+// list, rpO[x] (x <= n), and d+(x), from the orientation bits at its row
+// start; the heavy flag; code = d+(x) if x is a light source (light,
+// d+ >= 2), else 0 (in a union of components, m' is that of x's component:
+// mk[comp[x]]); rowQ[x] = (start of
 // N+(x), code ? d+ : ~d+, deg, 0), what the anchor work gathers of a vertex in
 // one 16-byte load; rpD[x], the first slot of x's v-major descriptors: the
 // in-degrees d- = deg - d+ of the vertices before x, that is x's row start in
 // the counted graph (row) minus its start in the up lists (rpO); and
 // cw[x] = rpD[x] << 32 (see claim_vmajor).  Also clears the counts of the
 // three wide-list classes, wide[c * (n + 1)].
-__global__ void k_vertex_prep(int64_t n, const int32_t* __restrict__ degp, const int32_t* __restrict__ dplus,
+__global__ void k_vertex_prep(int64_t n, int64_t E2, const uint64_t* __restrict__ ubits,
+                              const int32_t* __restrict__ upre, const int32_t* __restrict__ degp,
                               const int32_t* __restrict__ mp_dev, const int32_t* __restrict__ comp,
-                              const int64_t* __restrict__ mk, int32_t ha, int32_t hb,
-                              const int32_t* __restrict__ rpO, const int32_t* __restrict__ row,
-                              int32_t* __restrict__ heavy, int32_t* __restrict__ code, int32_t* __restrict__ rpD,
-                              int4* __restrict__ rowQ, unsigned long long* __restrict__ cw,
-                              int32_t* __restrict__ wide) {
+                              const int64_t* __restrict__ mk, int32_t ha, int32_t hb, const int32_t* __restrict__ row,
+                              int32_t* __restrict__ rpO, int32_t* __restrict__ dplus, int32_t* __restrict__ heavy,
+                              int32_t* __restrict__ code, int32_t* __restrict__ rpD, int4* __restrict__ rowQ,
+                              unsigned long long* __restrict__ cw, int32_t* __restrict__ wide) {
     const int64_t mp = comp ? 0 : mp_dev[0];
     if (blockIdx.x == 0 && threadIdx.x < 3) wide[threadIdx.x * (n + 1)] = 0;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t r = rpO[x];
-        const int32_t dslot = row[x] - r;
+        const int32_t rx = row[x];
+        const int32_t r = up_before(rx, E2, ubits, upre);
+        rpO[x] = r;
+        const int32_t dslot = rx - r;
         rpD[x] = dslot;
         if (x == n) break;
+        const int32_t dp = up_before(row[x + 1], E2, ubits, upre) - r;
+        dplus[x] = dp;
         const int32_t dg = degp[x];
         const bool hv = dg > 0 && is_heavy(dg, comp ? mk[comp[x]] : mp, ha, hb);
         heavy[x] = hv ? 1 : 0;
-        const int32_t dp = dplus[x];
         const int32_t c = !hv && dp >= 2 ? dp : 0;
         code[x] = c;
         rowQ[x] = make_int4(r, c ? c : ~dp, dg, 0);
@@ -2023,8 +2039,19 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
               (const uint8_t*)cls.get(), ncls, degp, ubits.get(), upre.get());
     scan_exclusive_i32(upre.get(), upre.get(), NW, s);
     const int32_t* mp_dev = upre.get() + NW;  // number of up entries = m'
+    // up-list starts and d+ at every row start, and the per-vertex fields of
+    // the light phase (classification of each vertex, its rowQ and v-major
+    // slot counter), in one pass
     DevBuf<int32_t> rpO(n + 1, s), dplus(n, s);
-    positions_at_rows(v_row, n, E2, ubits.get(), upre.get(), rpO.get(), dplus.get(), s);
+    DevBuf<int32_t> heavy(n + 1, s), code(n, s), rpD(n + 1, s);
+    DevBuf<int4> rowQ(n, s);
+    DevBuf<int64_t> Wu(n, s), cw(n, s);
+    DevBuf<int32_t> wide(3 * (n + 1), s);  // vertices with d+ in (128, 256], (256, 512], > 512; counts first
+    unsigned long long* cwp = reinterpret_cast<unsigned long long*>(cw.get());
+    TC_LAUNCH("vertex_prep", k_vertex_prep, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n, E2,
+              (const uint64_t*)ubits.get(), (const int32_t*)upre.get(), degp, mp_dev, comp,
+              un ? un->mk : (const int64_t*)nullptr, cfg.heavy_num, cfg.heavy_den, v_row, rpO.get(), dplus.get(),
+              heavy.get(), code.get(), rpD.get(), rowQ.get(), cwp, wide.get());
     DevBuf<int32_t> colO(g->m, s);  // m' <= m
     // one descriptor per up entry: the anchor work writes every entry of every
     // light source's list, and only those lists are read
@@ -2034,15 +2061,6 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     // 3. classification; anchor work (each light source's N+(u) in rank
     //    order, one descriptor per pair); item lists
     const int32_t vcap = cfg.vmajor_cap;
-    DevBuf<int32_t> heavy(n + 1, s), code(n, s), rpD(n + 1, s);
-    DevBuf<int4> rowQ(n, s);
-    DevBuf<int64_t> Wu(n, s), cw(n, s);
-    DevBuf<int32_t> wide(3 * (n + 1), s);  // vertices with d+ in (128, 256], (256, 512], > 512; counts first
-    unsigned long long* cwp = reinterpret_cast<unsigned long long*>(cw.get());
-    TC_LAUNCH("vertex_prep", k_vertex_prep, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n, degp,
-              (const int32_t*)dplus.get(), mp_dev, comp, un ? un->mk : (const int64_t*)nullptr, cfg.heavy_num,
-              cfg.heavy_den, (const int32_t*)rpO.get(), v_row, heavy.get(), code.get(), rpD.get(), rowQ.get(), cwp,
-              wide.get());
     PhaseScope ph_light("light");
     DevBuf<int64_t> Gx(un ? n : 0, s);  // per-list gather statistic (unions)
     int64_t* gxp = un ? Gx.get() : nullptr;
