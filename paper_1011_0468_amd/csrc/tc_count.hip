@@ -1477,7 +1477,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
 // rank of each heavy vertex in (deg, id) order, by counting smaller keys: tile
 // (bx, by) compares heavy vertices bx*256.. with the kRankChunk keys by*kRankChunk..
 // and adds its counts into rank[] (zeroed beforehand)
-constexpr int kRankChunk = 256;
+constexpr int kRankChunk = 1024;
 
 // In a union of components (comp != nullptr) the order is (component, deg,
 // id): each component's heavy vertices take a contiguous range of ranks, in
@@ -1485,7 +1485,8 @@ constexpr int kRankChunk = 256;
 __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev,
                                                      int32_t hmax, const int32_t* __restrict__ degp,
                                                      const int32_t* __restrict__ comp, int32_t* __restrict__ rank) {
-    __shared__ int32_t kd[256], kx[256], kc[256];
+    __shared__ uint64_t kk[256];  // rank keys (deg, id) of the staged heavy vertices
+    __shared__ int32_t kc[256];   // and their components (unions)
     const int32_t h = heavy_count(h_dev, hmax);
     // tiles (256 heavy vertices) x (kRankChunk keys), taken with a static
     // stride by a persistent grid sized for the device's h
@@ -1493,22 +1494,31 @@ __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ 
     for (int64_t tile = blockIdx.x; tile < tx * ty; tile += gridDim.x) {  // block-uniform
         const int64_t i = (tile % tx) * 256 + threadIdx.x;
         const int64_t j0 = (tile / tx) * kRankChunk;
-        int32_t x = -1, dx = 0, cx = 0;
-        if (i < h) { x = hlist[i]; dx = degp[x]; cx = comp ? comp[x] : 0; }
+        int32_t cx = 0;
+        uint64_t key = 0;
+        if (i < h) {
+            const int32_t x = hlist[i];
+            key = rank_key(degp[x], x);
+            cx = comp ? comp[x] : 0;
+        }
         const int64_t j1 = min((int64_t)h, j0 + kRankChunk);
         int32_t r = 0;
         for (int64_t jb = j0; jb < j1; jb += 256) {
             const int64_t j = jb + threadIdx.x;
             if (j < j1) {
-                kx[threadIdx.x] = hlist[j];
-                kd[threadIdx.x] = degp[kx[threadIdx.x]];
-                kc[threadIdx.x] = comp ? comp[kx[threadIdx.x]] : 0;
+                const int32_t y = hlist[j];
+                kk[threadIdx.x] = rank_key(degp[y], y);
+                if (comp) kc[threadIdx.x] = comp[y];
             }
             __syncthreads();
             const int lim = (int)min((int64_t)256, j1 - jb);
-            if (i < h)
-                for (int q = 0; q < lim; ++q)
-                    r += (kc[q] < cx || (kc[q] == cx && rank_below(kd[q], kx[q], dx, x))) ? 1 : 0;
+            if (i < h) {
+                if (!comp) {
+                    for (int q = 0; q < lim; ++q) r += kk[q] < key ? 1 : 0;
+                } else {
+                    for (int q = 0; q < lim; ++q) r += (kc[q] < cx || (kc[q] == cx && kk[q] < key)) ? 1 : 0;
+                }
+            }
             __syncthreads();
         }
         if (i < h && r) atomicAdd(&rank[i], r);
