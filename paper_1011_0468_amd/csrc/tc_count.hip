@@ -231,16 +231,19 @@ __device__ __forceinline__ int32_t up_before(int64_t e, int64_t E2, const uint64
 // in-degrees d- = deg - d+ of the vertices before x, that is x's row start in
 // the counted graph (row) minus its start in the up lists (rpO); and
 // cw[x] = rpD[x] << 32 (see claim_vmajor).  Also clears the counts of the
-// three wide-list classes, wide[c * (n + 1)].
+// three wide-list classes, wide[c * (n + 1)], and stores the up lists'
+// sentinel (-2, past the last possible up entry).
 __global__ void k_vertex_prep(int64_t n, int64_t E2, const uint64_t* __restrict__ ubits,
                               const int32_t* __restrict__ upre, const int32_t* __restrict__ degp,
                               const int32_t* __restrict__ mp_dev, const int32_t* __restrict__ comp,
                               const int64_t* __restrict__ mk, int32_t ha, int32_t hb, const int32_t* __restrict__ row,
                               int32_t* __restrict__ rpO, int32_t* __restrict__ dplus, int32_t* __restrict__ heavy,
                               int32_t* __restrict__ code, int32_t* __restrict__ rpD, int4* __restrict__ rowQ,
-                              unsigned long long* __restrict__ cw, int32_t* __restrict__ wide) {
+                              unsigned long long* __restrict__ cw, int32_t* __restrict__ wide,
+                              int32_t* __restrict__ sentinel) {
     const int64_t mp = comp ? 0 : mp_dev[0];
     if (blockIdx.x == 0 && threadIdx.x < 3) wide[threadIdx.x * (n + 1)] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sentinel = -2;  // read by the closure past a range's positions
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t rx = row[x];
         const int32_t r = up_before(rx, E2, ubits, upre);
@@ -930,15 +933,16 @@ __device__ __forceinline__ int find_list(const int32_t* P, int d, int32_t g) {
 }
 
 
-// Membership tests of the keys x[k] of the lanes in the wave mask vm[k]
-// against the bucketed table; returns the number of hits in the whole wave
+// Membership tests of the keys x[k] against the bucketed table; returns the
+// number of hits in the whole wave
 // (wave-uniform).  One 16-byte read per key resolves it unless its home
 // bucket was passed over by an insert and does not hold it (about one bucket
 // in 300 at one key per bucket on average, one in 5000 at 0.6).  Every x[k]
-// is a vertex id (>= 0), also in lanes outside vm[k].
+// is a vertex id (>= 0) or, in lanes past the end of the positions, the
+// sentinel -2, which matches no slot (slots hold ids, -1 or a marked id,
+// whose low 31 bits are an id); such a lane can at most walk a marked run.
 template <int U>
-__device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const int32_t (&x)[U],
-                                              const uint64_t (&vm)[U]) {
+__device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const int32_t (&x)[U]) {
     const uint32_t mask = (1u << lg) - 1;
     const int4* t4 = reinterpret_cast<const int4*>(tab);
     uint32_t bk[U];
@@ -955,11 +959,10 @@ __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const 
         const int32_t v = x[k];
         // one compare per slot straight into a wave mask (no per-lane booleans)
         const uint64_t hit = (ballot64(e[k].x == v) | ballot64(e[k].y == v) | ballot64(e[k].z == v) |
-                              ballot64((e[k].w & kKeyBits) == v)) &
-                             vm[k];
+                              ballot64((e[k].w & kKeyBits) == v));
         const uint64_t passed = ballot64(e[k].w < -1);  // marked last slot
         found += (int32_t)__popcll(hit);
-        live[k] = vm[k] & passed & ~hit;
+        live[k] = passed & ~hit;
         any |= live[k];
     }
     if (any) {  // rare: home bucket passed over and without the key
@@ -995,18 +998,18 @@ __device__ __forceinline__ int32_t probe_many(const int32_t* tab, int lg, const 
 // one ballot and one mbcnt per strip of 64.  Whole wave.
 template <int U, bool GLOBAL>
 __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D, int nl, int32_t g0, int32_t b,
-                                              const int32_t* __restrict__ colO, uint8_t* mark, int lane, int& jlo,
-                                              int32_t (&x)[U], uint64_t (&vm)[U]) {
-    // every lane loads (lanes past b read colO[0], which exists whenever there
-    // are positions) and nothing consumes the loaded values before the probe,
-    // so these loads stay in flight across the caller's other work
+                                              const int32_t* __restrict__ colO, uint32_t sent, uint8_t* mark,
+                                              int lane, int& jlo, int32_t (&x)[U]) {
+    // every lane loads (lanes past b read colO[sent], which holds the sentinel
+    // -2) and nothing consumes the loaded values before the probe, so these
+    // loads stay in flight across the caller's other work
     const int32_t nxt = __builtin_amdgcn_readfirstlane(jlo + 1 < nl ? P[jlo + 1] : INT32_MAX);
     if (nxt >= g0 + 64 * U) {  // wave-uniform: one list covers the super-strip
         const int32_t d0 = D[jlo];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int32_t g = g0 + lane + 64 * k;
-            x[k] = *(const int32_t*)((const char*)colO + ((uint32_t)(g < b ? d0 + g : 0) << 2));
+            x[k] = *(const int32_t*)((const char*)colO + ((uint32_t)(g < b ? d0 + g : sent) << 2));
         }
     } else {
 #pragma unroll
@@ -1038,11 +1041,9 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int32_t g = g0 + lane + 64 * k;
-            x[k] = *(const int32_t*)((const char*)colO + ((uint32_t)(g < b ? dk[k] + g : 0) << 2));
+            x[k] = *(const int32_t*)((const char*)colO + ((uint32_t)(g < b ? dk[k] + g : sent) << 2));
         }
     }
-#pragma unroll
-    for (int k = 0; k < U; ++k) vm[k] = ballot64(g0 + lane + 64 * k < b);
 }
 
 // Closure tests for positions [a, b) of the concatenated streamed lists
@@ -1053,8 +1054,8 @@ __device__ __forceinline__ void gather_strips(const int32_t* P, const int32_t* D
 // most ranges are that short; elsewhere the extra code costs occupancy).
 template <int U, bool GLOBAL, bool SHORT>
 __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D, int nl, int32_t a, int32_t b,
-                                              const int32_t* __restrict__ colO, const int32_t* tab, int lg,
-                                              uint8_t* mark, int lane) {
+                                              const int32_t* __restrict__ colO, uint32_t sent, const int32_t* tab,
+                                              int lg, uint8_t* mark, int lane) {
     // a, b and nl are wave-uniform; saying so makes every exit of the
     // pipelined loop below a scalar branch.  Otherwise the loop is compiled
     // as a divergent one whose early exit reaches the loop head with the
@@ -1068,15 +1069,13 @@ __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D
     int jlo = a == 0 ? 0 : __builtin_amdgcn_readfirstlane(find_list(P, nl, a));  // P[0] = 0 owns position 0
     if (SHORT && b - a <= 64) {  // one strip
         int32_t x1[1];
-        uint64_t v1[1];
-        gather_strips<1, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, x1, v1);
-        return probe_many<1>(tab, lg, x1, v1);
+        gather_strips<1, GLOBAL>(P, D, nl, a, b, colO, sent, mark, lane, jlo, x1);
+        return probe_many<1>(tab, lg, x1);
     }
     if (SHORT && b - a <= 64 * U) {  // one super-strip
         int32_t x1[U];
-        uint64_t v1[U];
-        gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, x1, v1);
-        return probe_many<U>(tab, lg, x1, v1);
+        gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, sent, mark, lane, jlo, x1);
+        return probe_many<U>(tab, lg, x1);
     }
     // super-strips i = 0 .. ns-1 start at a + i 64U.  The loop runs whole
     // pairs and has one exit, where only set a is in flight; the last one or
@@ -1084,21 +1083,20 @@ __device__ __forceinline__ int32_t close_flat(const int32_t* P, const int32_t* D
     constexpr int32_t S = 64 * U;
     const int32_t ns = (b - a + S - 1) / S;
     int32_t xa[U], xb[U];
-    uint64_t va[U], vb[U];
-    gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, mark, lane, jlo, xa, va);
+    gather_strips<U, GLOBAL>(P, D, nl, a, b, colO, sent, mark, lane, jlo, xa);
     int32_t i = 0;
     for (; i + 2 < ns; i += 2) {
-        gather_strips<U, GLOBAL>(P, D, nl, a + (i + 1) * S, b, colO, mark, lane, jlo, xb, vb);
-        cnt += probe_many<U>(tab, lg, xa, va);
-        gather_strips<U, GLOBAL>(P, D, nl, a + (i + 2) * S, b, colO, mark, lane, jlo, xa, va);
-        cnt += probe_many<U>(tab, lg, xb, vb);
+        gather_strips<U, GLOBAL>(P, D, nl, a + (i + 1) * S, b, colO, sent, mark, lane, jlo, xb);
+        cnt += probe_many<U>(tab, lg, xa);
+        gather_strips<U, GLOBAL>(P, D, nl, a + (i + 2) * S, b, colO, sent, mark, lane, jlo, xa);
+        cnt += probe_many<U>(tab, lg, xb);
     }
     if (i + 1 < ns) {
-        gather_strips<U, GLOBAL>(P, D, nl, a + (i + 1) * S, b, colO, mark, lane, jlo, xb, vb);
-        cnt += probe_many<U>(tab, lg, xa, va);
-        cnt += probe_many<U>(tab, lg, xb, vb);
+        gather_strips<U, GLOBAL>(P, D, nl, a + (i + 1) * S, b, colO, sent, mark, lane, jlo, xb);
+        cnt += probe_many<U>(tab, lg, xa);
+        cnt += probe_many<U>(tab, lg, xb);
     } else {
-        cnt += probe_many<U>(tab, lg, xa, va);
+        cnt += probe_many<U>(tab, lg, xa);
     }
     return cnt;
 }
@@ -1207,7 +1205,8 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
                                                       const int32_t* __restrict__ rpD,
                                                       const unsigned long long* __restrict__ cw,
                                                       const int2* __restrict__ packU, const int2* __restrict__ packD,
-                                                      const int32_t* __restrict__ comp, int64_t* __restrict__ acc) {
+                                                      uint32_t sent, const int32_t* __restrict__ comp,
+                                                      int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 4 * DS;                                     // buckets of 4 slots, load <= 1/4
     static_assert((DS & (DS - 1)) == 0 && DS >= 16, "DS: a power of two");
     constexpr int kLgDS = __builtin_ctz(DS);                           // the table region holds 2^kLgDS buckets
@@ -1282,7 +1281,7 @@ __global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ it
             const int32_t nl = stage_loaded<64>(st, ln, P, D, nullptr, lane, &W);
             wave_lds_sync();
             if (more) body(rs2, d2, L2, cnt2, kv, st, ln);  // in flight during the closure
-            total += close_flat<kU, false, true>(P, D, nl, 0, W, colO, tab, lg, mark, lane);  // wave-uniform
+            total += close_flat<kU, false, true>(P, D, nl, 0, W, colO, sent, tab, lg, mark, lane);  // wave-uniform
             wave_lds_sync();
             xa = xa2;
             rs = rs2;
@@ -1413,7 +1412,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
                                                       const int32_t* __restrict__ rpD,
                                                       const unsigned long long* __restrict__ cw,
                                                       const int2* __restrict__ packU, const int2* __restrict__ packD,
-                                                      int32_t dcap, int32_t* __restrict__ gscratch,
+                                                      int32_t dcap, int32_t* __restrict__ gscratch, uint32_t sent,
                                                       const int32_t* __restrict__ comp, int64_t* __restrict__ acc) {
     extern __shared__ __attribute__((aligned(16))) int32_t dyn[];
     __shared__ int32_t red[5];
@@ -1464,7 +1463,7 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
         const int32_t q = (W + 3) / 4;
         const int32_t a = min(w * q, W);
         const int32_t b = min(a + q, W);
-        total += close_flat<kU, GLOBAL, false>(P, D, nl, a, b, colO, tab, lg, mark, lane);  // wave-uniform
+        total += close_flat<kU, GLOBAL, false>(P, D, nl, a, b, colO, sent, tab, lg, mark, lane);  // wave-uniform
         __syncthreads();
     }
     flush_tl(acc, cur, total, lane);
@@ -2053,6 +2052,10 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     // the light phase (classification of each vertex, its rowQ and v-major
     // slot counter), in one pass
     DevBuf<int32_t> rpO(n + 1, s), dplus(n, s);
+    // up lists: m' <= m entries, then the sentinel -2 at index m, which the
+    // closure's gathers read for positions past a range
+    DevBuf<int32_t> colO(g->m + 1, s);
+    const uint32_t sent = (uint32_t)g->m;
     DevBuf<int32_t> heavy(n + 1, s), code(n, s), rpD(n + 1, s);
     DevBuf<int4> rowQ(n, s);
     DevBuf<int64_t> Wu(n, s), cw(n, s);
@@ -2061,8 +2064,8 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
     TC_LAUNCH("vertex_prep", k_vertex_prep, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n, E2,
               (const uint64_t*)ubits.get(), (const int32_t*)upre.get(), degp, mp_dev, comp,
               un ? un->mk : (const int64_t*)nullptr, cfg.heavy_num, cfg.heavy_den, v_row, rpO.get(), dplus.get(),
-              heavy.get(), code.get(), rpD.get(), rowQ.get(), cwp, wide.get());
-    DevBuf<int32_t> colO(g->m, s);  // m' <= m
+              heavy.get(), code.get(), rpD.get(), rowQ.get(), cwp, wide.get(), colO.get() + sent);
+
     // one descriptor per up entry: the anchor work writes every entry of every
     // light source's list, and only those lists are read
     DevBuf<int2> packU(g->m, s);
@@ -2161,7 +2164,7 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
         TC_LAUNCH("light_small", kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                   (const int2*)items.get(), (const int32_t*)sbase.get() + n, (const int32_t*)rpO.get(),
                   (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
-                  (const int2*)packU.get(), (const int2*)packD.get(), comp, acc);
+                  (const int2*)packU.get(), (const int2*)packD.get(), sent, comp, acc);
     }
     auto launch_large = [&](const DevBuf<int2>& items, const DevBuf<int32_t>& base, int32_t dcap, bool global) {
         // tab: 4 * next_pow2(d) <= 4 * dcap slots, P: kJL+1, D: kJL, flags: 4*64*kU (16-byte multiple)
@@ -2186,7 +2189,8 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
             TC_LAUNCH("light_large", kernel, dim3((unsigned)blocks), dim3(256), lds_bytes, s,
                       (const int2*)items.get(), (const int32_t*)base.get() + n, (const int32_t*)rpO.get(),
                       (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
-                      (const int2*)packU.get(), (const int2*)packD.get(), dcap, (int32_t*)nullptr, comp, acc);
+                      (const int2*)packU.get(), (const int2*)packD.get(), dcap, (int32_t*)nullptr, sent, comp,
+                      acc);
         } else {
             const int64_t blocks = (int64_t)num_cus();
             DevBuf<int32_t> gscr((size_t)blocks * per_block, s);
@@ -2194,7 +2198,7 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
             TC_LAUNCH("light_huge", kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                       (const int2*)items.get(), (const int32_t*)base.get() + n, (const int32_t*)rpO.get(),
                       (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
-                      (const int2*)packU.get(), (const int2*)packD.get(), dcap, gscr.get(), comp, acc);
+                      (const int2*)packU.get(), (const int2*)packD.get(), dcap, gscr.get(), sent, comp, acc);
         }
     };
     if (plan.dcap_lds) launch_large(items_l, lbase, plan.dcap_lds, false);
@@ -2295,7 +2299,7 @@ int64_t count_bytes(int64_t n, int64_t m, int32_t maxd, int sampled, const Count
     if (sampled)  // keep bits and prefix, rows, degrees, entries, staged entries
         b += rb(8 * NW) + rb(4 * (NW + 1)) + rb(4 * (n + 1)) + rb(4 * n) + 4 * rb(4 * E2) + scan_scratch_bytes(NW);
     b += rb(n) + rb(8 * NW) + rb(4 * (NW + 1)) + scan_scratch_bytes(NW);  // degree classes, orientation bits
-    b += rb(4 * (n + 1)) + rb(4 * n) + rb(4 * m);                  // rpO, d+, up lists
+    b += rb(4 * (n + 1)) + rb(4 * n) + rb(4 * (m + 1));            // rpO, d+, up lists and their sentinel
     b += 2 * rb(4 * (n + 1)) + rb(4 * n);                          // heavy, code, descriptor slots
     b += rb(16 * n) + 2 * rb(8 * n) + rb(12 * (n + 1));            // rowQ, Wu, cw, wide-list vertices
     b += rb(8 * m) + rb(8 * (cfg.vmajor_cap > 0 ? m : 1));         // packed descriptors
