@@ -429,7 +429,7 @@ __device__ __forceinline__ void work_groups(uint64_t mask, const int4& q, int64_
         int32_t idx = lane;
         bitonic_lanes<G>(key, idx, lane);
         // rowQ of the vertex that lands on this lane, from the lane that loaded it
-        const int4 qv = make_int4(__shfl(qw.x, idx, 64), __shfl(qw.y, idx, 64), 0, __shfl(qw.w, idx, 64));
+        const int4 qv = make_int4(__shfl(qw.x, idx, 64), __shfl(qw.y, idx, 64), 0, 0);  // (start, code) are what pair_desc reads
         int64_t wu = 0, gl = 0;
         if (in) {
             const int32_t v = (int32_t)(uint32_t)key;
@@ -2232,10 +2232,11 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
         TC_LAUNCH("heavy_transpose", k_heavy_transpose, dim3((unsigned)std::min<int64_t>(
                                                             (hp_max / 64) * (hp_max / 64), (int64_t)num_cus() * 8)),
                   dim3(256), 0, s, h_dev, hm, (const uint8_t*)U.get(), UT.get());
-        // one block per macro tile up to 8 per CU, a multiple of 8 (one share per XCD)
+        // one block per macro tile up to 16 per CU (blocks beyond the resident ones
+        // start as others finish), a multiple of 8 (one share per XCD)
         const int64_t nm_max = hp_max / kHT;
         const int64_t tiles_max = nm_max * (nm_max + 1) / 2;
-        const int64_t mblocks = std::min<int64_t>((int64_t)num_cus() * 8, (tiles_max + 7) / 8 * 8);
+        const int64_t mblocks = std::min<int64_t>((int64_t)num_cus() * 16, (tiles_max + 7) / 8 * 8);
         TC_LAUNCH("heavy_mfma", k_heavy_mfma, dim3((unsigned)mblocks), dim3(256), 0, s, (const uint8_t*)U.get(),
                   (const uint8_t*)UT.get(), h_dev, hm, acc);
     }
