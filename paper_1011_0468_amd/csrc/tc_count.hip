@@ -1197,16 +1197,17 @@ __device__ __forceinline__ void flush_tl(int64_t* acc, int32_t c, int64_t total,
 }
 
 // UNION: the graph is a union of components (comp[x] of every vertex), and
-// each item's closures count towards its anchor's component.
+// each item's closures count towards its anchor's component.  That variant
+// is held to 7 waves per SIMD (72 VGPRs, as the other one compiles to), so
+// that 7 blocks per CU (17.5 KB of LDS each) stay resident; left alone it
+// takes 76 VGPRs and fits only 6.
 template <int DS, bool UNION>
-__global__ void __launch_bounds__(256) k_light_small(const int2* __restrict__ items,
-                                                      const int32_t* __restrict__ n_items_dev,
-                                                      const int32_t* __restrict__ rpO, const int32_t* __restrict__ colO,
-                                                      const int32_t* __restrict__ rpD,
-                                                      const unsigned long long* __restrict__ cw,
-                                                      const int2* __restrict__ packU, const int2* __restrict__ packD,
-                                                      uint32_t sent, const int32_t* __restrict__ comp,
-                                                      int64_t* __restrict__ acc) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UNION ? 7 : 1)))
+k_light_small(const int2* __restrict__ items, const int32_t* __restrict__ n_items_dev, const int32_t* __restrict__ rpO,
+              const int32_t* __restrict__ colO, const int32_t* __restrict__ rpD,
+              const unsigned long long* __restrict__ cw, const int2* __restrict__ packU,
+              const int2* __restrict__ packD, uint32_t sent, const int32_t* __restrict__ comp,
+              int64_t* __restrict__ acc) {
     constexpr int HS_MAX = 4 * DS;                                     // buckets of 4 slots, load <= 1/4
     static_assert((DS & (DS - 1)) == 0 && DS >= 16, "DS: a power of two");
     constexpr int kLgDS = __builtin_ctz(DS);                           // the table region holds 2^kLgDS buckets
@@ -1474,25 +1475,24 @@ __global__ void __launch_bounds__(256) k_light_large(const int2* __restrict__ it
 // ---------------------------------------------------------------------------
 
 // rank of each heavy vertex in (deg, id) order, by counting smaller keys: tile
-// (bx, by) compares heavy vertices bx*256.. with the kRankChunk keys by*kRankChunk..
-// and adds its counts into rank[] (zeroed beforehand)
-constexpr int kRankChunk = 1024;
+// (bx, by) compares heavy vertices bx*256.. with the `chunk` keys by*chunk..
+// (a multiple of 256) and adds its counts into rank[] (zeroed beforehand)
 
 // In a union of components (comp != nullptr) the order is (component, deg,
 // id): each component's heavy vertices take a contiguous range of ranks, in
 // their own (deg, id) order, so U is block diagonal.
 __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ hlist, const int32_t* __restrict__ h_dev,
-                                                     int32_t hmax, const int32_t* __restrict__ degp,
+                                                     int32_t hmax, int32_t chunk, const int32_t* __restrict__ degp,
                                                      const int32_t* __restrict__ comp, int32_t* __restrict__ rank) {
     __shared__ uint64_t kk[256];  // rank keys (deg, id) of the staged heavy vertices
     __shared__ int32_t kc[256];   // and their components (unions)
     const int32_t h = heavy_count(h_dev, hmax);
-    // tiles (256 heavy vertices) x (kRankChunk keys), taken with a static
+    // tiles (256 heavy vertices) x (chunk keys), taken with a static
     // stride by a persistent grid sized for the device's h
-    const int64_t tx = (h + 255) / 256, ty = (h + kRankChunk - 1) / kRankChunk;
+    const int64_t tx = (h + 255) / 256, ty = (h + chunk - 1) / chunk;
     for (int64_t tile = blockIdx.x; tile < tx * ty; tile += gridDim.x) {  // block-uniform
         const int64_t i = (tile % tx) * 256 + threadIdx.x;
-        const int64_t j0 = (tile / tx) * kRankChunk;
+        const int64_t j0 = (tile / tx) * chunk;
         int32_t cx = 0;
         uint64_t key = 0;
         if (i < h) {
@@ -1500,7 +1500,7 @@ __global__ void __launch_bounds__(256) k_heavy_rank(const int32_t* __restrict__ 
             key = rank_key(degp[x], x);
             cx = comp ? comp[x] : 0;
         }
-        const int64_t j1 = min((int64_t)h, j0 + kRankChunk);
+        const int64_t j1 = min((int64_t)h, j0 + chunk);
         int32_t r = 0;
         for (int64_t jb = j0; jb < j1; jb += 256) {
             const int64_t j = jb + threadIdx.x;
@@ -1902,6 +1902,26 @@ static LightPlan light_plan(int64_t m, int32_t maxd, const CountConfig& cfg) {
     return pl;
 }
 
+// Keys per rank tile for h heavy vertices: the largest of 1024, 512 and 256
+// that still gives every CU a tile (longer chunks take fewer rank atomics,
+// shorter ones more tiles when h is small).
+static int32_t rank_chunk(int64_t h) {
+    for (int32_t c = 1024; c > 256; c /= 2)
+        if ((int64_t)ceil_div(h, 256) * (int64_t)ceil_div(h, c) >= num_cus()) return c;
+    return 256;
+}
+
+// Blocks of 256 threads of `kernel` that stay resident on one CU with
+// `lds_bytes` of dynamic LDS (at least 1).  Persistent launches take at most
+// this many per CU, queried for the very variant they launch: the variants
+// of one kernel need not compile to the same register count.
+template <typename K>
+static int resident_blocks(K kernel, size_t lds_bytes) {
+    int r = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, kernel, 256, lds_bytes) != hipSuccess || r < 1) r = 1;
+    (void)hipGetLastError();
+    return r;
+}
 
 // Heavy phase of a union of components: the heavy counts at the component
 // starts are read back (one synchronisation), and each component with at
@@ -1953,10 +1973,11 @@ static void count_union_heavy(const tc_graph_s* g, const CountUnion& un, const C
     TC_LAUNCH("heavy_list", k_heavy_list, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t*)heavy.get(),
               (const int32_t*)hpos.get(), hm, hlist.get(), acc);
     fill_i32(hrank.get(), 0, H, s);
+    const int32_t chunk = rank_chunk(H);
     TC_LAUNCH("heavy_rank", k_heavy_rank, dim3((unsigned)std::min<int64_t>(
-                                              (int64_t)ceil_div(H, 256) * (int64_t)ceil_div(H, kRankChunk),
+                                              (int64_t)ceil_div(H, 256) * (int64_t)ceil_div(H, chunk),
                                               (int64_t)num_cus() * 4)),
-              dim3(256), 0, s, (const int32_t*)hlist.get(), h_dev, hm, degp, un.comp, hrank.get());
+              dim3(256), 0, s, (const int32_t*)hlist.get(), h_dev, hm, chunk, degp, un.comp, hrank.get());
     TC_LAUNCH("heavy_place", k_heavy_place, dim3(ceil_div(H, 256)), dim3(256), 0, s, (const int32_t*)hlist.get(),
               h_dev, hm, (const int32_t*)hrank.get(), hidx.get(), horder.get());
     DevBuf<uint8_t> U((size_t)ubytes, s), UT((size_t)ubytes, s);
@@ -2133,14 +2154,8 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
               (const unsigned long long*)cwp, (const int32_t*)rpD.get(), items_t.get(), items_s.get(), items_l.get(),
               items_h.get());
     {
-        static const int resident = [] {
-            int r = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_light_tiny<false>, 256, 0) != hipSuccess || r < 1)
-                r = 1;
-            (void)hipGetLastError();
-            return r;
-        }();
-        const int64_t blocks = (int64_t)num_cus() * std::min<int32_t>(cfg.light_blocks_per_cu, resident);
+        static const int resident[2] = {resident_blocks(k_light_tiny<false>, 0), resident_blocks(k_light_tiny<true>, 0)};
+        const int64_t blocks = (int64_t)num_cus() * std::min<int32_t>(cfg.light_blocks_per_cu, resident[un ? 1 : 0]);
         auto kernel = un ? k_light_tiny<true> : k_light_tiny<false>;
         TC_LAUNCH("light_tiny", kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const int2*)items_t.get(),
                   (const int32_t*)tbase.get() + n, (const int32_t*)rpO.get(), (const int32_t*)colO.get(),
@@ -2151,15 +2166,10 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
         const DevBuf<int2>& items = items_s;
         // a persistent grid larger than what stays resident would run its last
         // blocks in a second round: cap the blocks per CU at the resident count
-        static const int resident = [] {
-            int r = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_light_small<128, false>, 256, 0) != hipSuccess ||
-                r < 1)
-                r = 1;
-            (void)hipGetLastError();
-            return r;
-        }();
-        const int64_t blocks = (int64_t)num_cus() * std::min<int32_t>(cfg.light_blocks_per_cu, resident);
+        // of the variant launched
+        static const int resident[2] = {resident_blocks(k_light_small<128, false>, 0),
+                                        resident_blocks(k_light_small<128, true>, 0)};
+        const int64_t blocks = (int64_t)num_cus() * std::min<int32_t>(cfg.light_blocks_per_cu, resident[un ? 1 : 0]);
         auto kernel = un ? k_light_small<128, true> : k_light_small<128, false>;
         TC_LAUNCH("light_small", kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                   (const int2*)items.get(), (const int32_t*)sbase.get() + n, (const int32_t*)rpO.get(),
@@ -2172,20 +2182,18 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
         const size_t lds_bytes = sizeof(int32_t) * per_block;
         if (!global) {
             // one round of resident blocks (LDS and registers permitting, at most 8 per CU)
-            static std::atomic<int> resident[16];  // by log2(dcap); every thread computes the same value
+            // by variant and log2(dcap); every thread computes the same value
+            static std::atomic<int> resident[2][16];
             int lgc = 0;
             while ((1 << lgc) < dcap) ++lgc;
-            int r = resident[lgc].load(std::memory_order_relaxed);
+            auto kernel = un ? k_light_large<false, true> : k_light_large<false, false>;
+            int r = resident[un ? 1 : 0][lgc].load(std::memory_order_relaxed);
             if (!r) {
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_light_large<false, false>, 256, lds_bytes) !=
-                        hipSuccess || r < 1)
-                    r = 1;
-                (void)hipGetLastError();
-                resident[lgc].store(r, std::memory_order_relaxed);
+                r = resident_blocks(kernel, lds_bytes);
+                resident[un ? 1 : 0][lgc].store(r, std::memory_order_relaxed);
             }
             const int64_t per_cu = std::min(r, 8);
             const int64_t blocks = (int64_t)num_cus() * per_cu;
-            auto kernel = un ? k_light_large<false, true> : k_light_large<false, false>;
             TC_LAUNCH("light_large", kernel, dim3((unsigned)blocks), dim3(256), lds_bytes, s,
                       (const int2*)items.get(), (const int32_t*)base.get() + n, (const int32_t*)rpO.get(),
                       (const int32_t*)colO.get(), (const int32_t*)rpD.get(), (const unsigned long long*)cwp,
@@ -2218,11 +2226,12 @@ static void count_impl(const tc_graph_s* g, int sampled, uint64_t thr, uint64_t 
                   (const int32_t*)heavy.get(), (const int32_t*)hpos.get(), hm, hlist.get(), acc);
         DevBuf<int32_t> hrank(hmax, s);
         fill_i32(hrank.get(), 0, hmax, s);
+        const int32_t chunk = rank_chunk(hmax);
         TC_LAUNCH("heavy_rank", k_heavy_rank, dim3((unsigned)std::min<int64_t>(
-                                                  (int64_t)ceil_div(hmax, 256) * (int64_t)ceil_div(hmax, kRankChunk),
+                                                  (int64_t)ceil_div(hmax, 256) * (int64_t)ceil_div(hmax, chunk),
                                                   (int64_t)num_cus() * 4)),
                   dim3(256), 0, s,
-                  (const int32_t*)hlist.get(), h_dev, hm, degp, (const int32_t*)nullptr, hrank.get());
+                  (const int32_t*)hlist.get(), h_dev, hm, chunk, degp, (const int32_t*)nullptr, hrank.get());
         TC_LAUNCH("heavy_place", k_heavy_place, dim3(ceil_div(hmax, 256)), dim3(256), 0, s,
                   (const int32_t*)hlist.get(), h_dev, hm, (const int32_t*)hrank.get(), hidx.get(), horder.get());
         DevBuf<uint8_t> U((size_t)hp_max * hp_max, s), UT((size_t)hp_max * hp_max, s);
