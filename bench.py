@@ -814,7 +814,7 @@ def _mfma_ops(h):
 def phase_breakdown(tc, step, res, info, csr_ms, pairs):
     """One extra step with every launch bracketed by HIP events (outside the
     timed region): kernel time per step of the path, next to the bytes or
-    operations its model says it must move (SURVEY-style declared models:
+    operations its model says it must move (the declared per-phase models:
     sample 4*2m + 4(n+1) read + 4*2m' + 8(n+1) written; orientation and split
     4*2m' + 4(n+1) read + 4m' + 4(n+1) + 4n written; light closure: the list
     model; heavy block: executed int8 MFMA operations; CSR build 8 B per input
